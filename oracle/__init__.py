@@ -1,0 +1,166 @@
+"""FP64 CPU oracle for the coupled harmonic oscillator (arXiv 1702.02207).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the product library and its binding never
+do.  It shares no code with the HIP path.
+
+``osc_oracle.c`` holds the integrators (classic RK4 and velocity Verlet on the
+first-order system of section 3), the Cholesky formation of A = M^-1 K for
+eq. (1), the energy and the Verlet invariant.  ``closed_form.py`` holds the
+analytic results of section 2 (eq. (4)-(7)) and the exact discrete solutions of
+both schemes, which pin the C code to the mathematics.
+
+All arrays are float64, C-contiguous, instance-major: [batch, s]; frames are
+[nframes, batch, s] with nframes = nsteps // stride + 1 (stride > 0).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import closed_form  # noqa: F401  (re-exported)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboscoracle.so")
+_lib = None
+
+RK4, VERLET = 0, 1
+_METHODS = {"rk4": RK4, "verlet": VERLET}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(os.path.join(_HERE, "osc_oracle.c"))):
+        from . import build
+        build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    d = ctypes.POINTER(ctypes.c_double)
+    i64, i32 = ctypes.c_int64, ctypes.c_int
+    lib.oracle_chain.argtypes = [i32, i64, i32, d, d, d, d, d, i64, i64, d, d, d, d]
+    lib.oracle_dense.argtypes = [i32, i64, i32, i32, d, d, d, d, d, i64, i64, d, d, d, d]
+    lib.oracle_form_a.argtypes = [i32, d, d, d]
+    lib.oracle_energy_chain.argtypes = [i64, i32, d, d, d, d, d]
+    lib.oracle_energy_dense.argtypes = [i64, i32, i32, d, d, d, d, d]
+    lib.oracle_verlet_q_chain.argtypes = [i64, i32, d, d, d, d, d, d]
+    for f in ("oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
+              "oracle_energy_dense", "oracle_verlet_q_chain"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(st, what):
+    if st != 0:
+        raise OracleError(f"{what} failed with status {st}")
+
+
+def _nframes(nsteps, stride):
+    return nsteps // stride + 1 if stride > 0 else 0
+
+
+def chain(method, m, k, dt, x0, v0, nsteps, stride, frames=True):
+    """Integrate fixed-free chains (eq. (2) for s bodies).
+
+    Returns (x_frames, v_frames, x_end, v_end); frames are None when
+    ``frames`` is False or stride == 0."""
+    lib = _load()
+    m, k, dt, x0, v0 = map(_f64, (m, k, dt, x0, v0))
+    batch, s = x0.shape
+    nf = _nframes(nsteps, stride) if frames else 0
+    xf = np.empty((nf, batch, s)) if nf else None
+    vf = np.empty((nf, batch, s)) if nf else None
+    xe = np.empty((batch, s))
+    ve = np.empty((batch, s))
+    st = lib.oracle_chain(_METHODS[method], batch, s, _p(m), _p(k), _p(dt), _p(x0), _p(v0),
+                          int(nsteps), int(stride) if nf else 0, _p(xf), _p(vf), _p(xe), _p(ve))
+    _check(st, "oracle_chain")
+    return xf, vf, xe, ve
+
+
+def dense(method, M, K, dt, x0, v0, nsteps, stride, shared=True, frames=True):
+    """Integrate eq. (1) with full M, K (A = M^-1 K by Cholesky).  shared: M, K
+    are [s, s] and dt[0] is used for every instance."""
+    lib = _load()
+    M, K, dt, x0, v0 = map(_f64, (M, K, np.atleast_1d(dt), x0, v0))
+    batch, s = x0.shape
+    nf = _nframes(nsteps, stride) if frames else 0
+    xf = np.empty((nf, batch, s)) if nf else None
+    vf = np.empty((nf, batch, s)) if nf else None
+    xe = np.empty((batch, s))
+    ve = np.empty((batch, s))
+    st = lib.oracle_dense(_METHODS[method], batch, s, 1 if shared else 0, _p(M), _p(K), _p(dt),
+                          _p(x0), _p(v0), int(nsteps), int(stride) if nf else 0,
+                          _p(xf), _p(vf), _p(xe), _p(ve))
+    _check(st, "oracle_dense")
+    return xf, vf, xe, ve
+
+
+def form_a(M, K):
+    """A = M^-1 K via M = L L^T; raises OracleError (status 2) if M is not SPD."""
+    lib = _load()
+    M, K = _f64(M), _f64(K)
+    s = M.shape[0]
+    A = np.empty((s, s))
+    _check(lib.oracle_form_a(s, _p(M), _p(K), _p(A)), "oracle_form_a")
+    return A
+
+
+def energy_chain(m, k, x, v):
+    lib = _load()
+    m, k, x, v = map(_f64, (m, k, x, v))
+    batch, s = x.shape
+    E = np.empty(batch)
+    _check(lib.oracle_energy_chain(batch, s, _p(m), _p(k), _p(x), _p(v), _p(E)), "energy_chain")
+    return E
+
+
+def energy_dense(M, K, x, v, shared=True):
+    lib = _load()
+    M, K, x, v = map(_f64, (M, K, x, v))
+    batch, s = x.shape
+    E = np.empty(batch)
+    _check(lib.oracle_energy_dense(batch, s, 1 if shared else 0, _p(M), _p(K), _p(x), _p(v),
+                                   _p(E)), "energy_dense")
+    return E
+
+
+def verlet_q_chain(m, k, dt, x, v):
+    lib = _load()
+    m, k, dt, x, v = map(_f64, (m, k, dt, x, v))
+    batch, s = x.shape
+    Q = np.empty(batch)
+    _check(lib.oracle_verlet_q_chain(batch, s, _p(m), _p(k), _p(dt), _p(x), _p(v), _p(Q)),
+           "verlet_q_chain")
+    return Q
+
+
+def rel_traj_err(got, ref):
+    """Per-instance max-abs relative trajectory error:
+    max over frames and dofs of |got - ref| divided by max |ref|.
+    Arrays are [..., batch, s]; returns [batch]."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if got.ndim == 2:
+        got, ref = got[None], ref[None]
+    num = np.abs(got - ref).max(axis=(0, 2))
+    den = np.abs(ref).max(axis=(0, 2))
+    return num / np.where(den > 0, den, 1.0)

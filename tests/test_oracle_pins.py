@@ -1,0 +1,378 @@
+"""Pins of the FP64 oracle to what the paper and the mathematics fix.
+
+Every check compares the oracle's C loops with something computed another way:
+the paper's printed roots, closed forms derived from eq. (3)-(7), the exact
+discrete solutions of RK4 and Verlet on the normal modes (LAPACK eigenpairs),
+invariants and special cases.  None of them re-types the oracle's loops.
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from oracle import closed_form as cf
+from paper_1702_02207_amd import workloads
+
+
+def _read_golden(path):
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, val = line.split()
+        vals[key] = float(val)
+    return vals
+
+
+# ---------------------------------------------------------------- section 2 --
+
+def test_eq6_roots_match_paper_print(golden_dir):
+    g = _read_golden(os.path.join(golden_dir, "eq6_roots_paper.txt"))
+    wf, ws = cf.eq6_omegas(g["m"], g["C"])
+    assert abs(wf - g["omega_fast"]) / g["omega_fast"] < 5e-4
+    assert abs(ws - g["omega_slow"]) / g["omega_slow"] < 5e-4
+
+
+def test_eq6_roots_exact_values_and_residual():
+    m, C = 2.0, 2025.0
+    wf, ws = cf.eq6_omegas(m, C)
+    # (C/m)(3 +- sqrt5)/2 written independently of the quadratic formula
+    assert wf == pytest.approx(math.sqrt(C / m * (3 + math.sqrt(5)) / 2), rel=1e-14)
+    assert ws == pytest.approx(math.sqrt(C / m * (3 - math.sqrt(5)) / 2), rel=1e-14)
+    for w in (wf, ws):
+        lam2 = -w * w
+        res = m * m * lam2 ** 2 + 3 * m * C * lam2 + C * C
+        assert abs(res) < 1e-9 * C * C
+
+
+def test_eq6_matches_generalised_eigenproblem():
+    m, C = 2.0, 2025.0
+    M, K = cf.chain_matrices([m, m], [C, C])
+    w = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True))
+    wf, ws = cf.eq6_omegas(m, C)
+    np.testing.assert_allclose(np.sort(w), [ws, wf], rtol=1e-13)
+
+
+def test_chain_matrices_reduce_to_eq2_and_eq3():
+    m1, m2, c1, c2 = 1.5, 0.7, 300.0, 55.0
+    M, K = cf.chain_matrices([m1, m2], [c1, c2])
+    # eq. (2): m1 x1'' + C1 x1 - C2 (x2 - x1) = 0, m2 x2'' + C2 (x2 - x1) = 0
+    np.testing.assert_array_equal(K, [[c1 + c2, -c2], [-c2, c2]])
+    np.testing.assert_array_equal(M, np.diag([m1, m2]))
+
+
+def test_eq4_mode_shapes():
+    m, C = 2.0, 2025.0
+    wf, ws = cf.eq6_omegas(m, C)
+    rf, rs = cf.eq4_mode_ratio(m, C, wf), cf.eq4_mode_ratio(m, C, ws)
+    assert rf == pytest.approx((1 - math.sqrt(5)) / 2, rel=1e-13)
+    assert rs == pytest.approx((1 + math.sqrt(5)) / 2, rel=1e-13)
+    # second row of eq. (4) holds for the same shape
+    for w, r in ((wf, rf), (ws, rs)):
+        assert abs(-C * 1.0 + (-m * w * w + C) * r) < 1e-9 * C
+
+
+def test_uniform_chain_formula_matches_eigvals():
+    for s in (1, 2, 3, 7, 16):
+        M, K = cf.chain_matrices(np.full(s, 1.3), np.full(s, 410.0))
+        w = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True))
+        np.testing.assert_allclose(w, cf.uniform_chain_omegas(s, 410.0, 1.3), rtol=1e-12)
+
+
+def test_two_mass_closed_form_is_modal_superposition():
+    """eq. (7) read as a modal superposition equals the eq. (3)/(4) closed form."""
+    t = np.linspace(0, 1, 57)
+    M, K = cf.chain_matrices([2.0, 2.0], [2025.0, 2025.0])
+    for x0, v0 in (((1.0, 0.0), (0.0, 0.0)), ((2.0, -3.0), (0.5, 1.0))):
+        xa, va = cf.two_mass_equal(t, 2.0, 2025.0, x0, v0)
+        xb, vb = cf.modal_solution(t, M, K, x0, v0)
+        np.testing.assert_allclose(xa, xb, atol=1e-12)
+        np.testing.assert_allclose(va, vb, atol=1e-10)
+
+
+# ---------------------------------------------------- C1: the paper's system --
+
+@pytest.mark.parametrize("x0", [(1.0, 0.0), (2.0, -3.0)])
+def test_c1_rk4_matches_closed_form(x0):
+    """configs[0]: eq. (3), m = 2, C = 2025, dt = 1e-5, 1e5 RK4 steps in FP64;
+    (2, -3) are the initial conditions of the paper's MATLAB run (section 3)."""
+    w = workloads.c1_paper_two_mass(x0=x0, out_stride=100)
+    xf, vf, xe, ve = oracle.chain("rk4", w.m, w.k, w.dt, w.x0, w.v0, w.nsteps, w.out_stride)
+    t = np.arange(xf.shape[0]) * w.out_stride * w.dt[0]
+    xa, va = cf.two_mass_equal(t, 2.0, 2025.0, x0, (0.0, 0.0))
+    assert oracle.rel_traj_err(xf, xa[:, None, :])[0] < 1e-10
+    assert oracle.rel_traj_err(vf, va[:, None, :])[0] < 1e-10
+    np.testing.assert_array_equal(xf[-1], xe)
+    if x0 == (1.0, 0.0):
+        # t = 1 values of the closed form (x1, x2), written out independently:
+        # x1 = (5+sqrt5)/10 cos wf t + (5-sqrt5)/10 cos ws t, x2 = (cos ws t - cos wf t)/sqrt5
+        wf, ws = cf.eq6_omegas(2.0, 2025.0)
+        s5 = math.sqrt(5)
+        x1 = (5 + s5) / 10 * math.cos(wf) + (5 - s5) / 10 * math.cos(ws)
+        x2 = (math.cos(ws) - math.cos(wf)) / s5
+        np.testing.assert_allclose(xe[0], [x1, x2], rtol=0, atol=1e-10)
+        E = oracle.energy_chain(w.m, w.k, w.x0, w.v0)
+        assert E[0] == 2025.0
+
+
+# ------------------------------------------------ exact discrete solutions ----
+
+def _random_chain(rng, s):
+    m = rng.uniform(0.5, 2.0, s)
+    k = np.exp(rng.uniform(math.log(1e2), math.log(1e4), s))
+    return m, k
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+@pytest.mark.parametrize("s", [1, 2, 3, 5, 8])
+def test_chain_matches_discrete_closed_form(method, s):
+    """At theta_max = w_max h = 0.5 the scheme differs from the exact flow by
+    O(1e-3), so this pins the RK4 tableau / Verlet splitting, not just
+    convergence."""
+    rng = np.random.default_rng(100 + s)
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    wmax = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    h = 0.5 / wmax
+    x0, v0 = rng.normal(size=s), rng.normal(size=s) * wmax
+    n, stride = 300, 7
+    xf, vf, _, _ = oracle.chain(method, m[None], k[None], [h], x0[None], v0[None], n, stride)
+    steps = np.arange(0, n + 1, stride)
+    ref = cf.rk4_discrete if method == "rk4" else cf.verlet_discrete
+    xr, vr = ref(steps, h, M, K, x0, v0)
+    assert oracle.rel_traj_err(xf, xr[:, None, :])[0] < 1e-11
+    assert oracle.rel_traj_err(vf, vr[:, None, :])[0] < 1e-11
+    exact_x, _ = cf.modal_solution(steps * h, M, K, x0, v0)
+    assert oracle.rel_traj_err(xf, exact_x[:, None, :])[0] > 1e-5   # the scheme is visible
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+@pytest.mark.parametrize("s", [1, 2, 4, 6])
+def test_dense_matches_discrete_closed_form(method, s):
+    rng = np.random.default_rng(200 + s)
+    M, K = workloads.random_dense_system(rng, s)
+    wmax = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    h = 0.4 / wmax
+    x0, v0 = rng.normal(size=(3, s)), rng.normal(size=(3, s))
+    n, stride = 250, 25
+    xf, vf, _, _ = oracle.dense(method, M, K, [h], x0, v0, n, stride)
+    steps = np.arange(0, n + 1, stride)
+    ref = cf.rk4_discrete if method == "rk4" else cf.verlet_discrete
+    for b in range(3):
+        xr, vr = ref(steps, h, M, K, x0[b], v0[b])
+        assert oracle.rel_traj_err(xf[:, b:b + 1], xr[:, None, :])[0] < 1e-11
+        assert oracle.rel_traj_err(vf[:, b:b + 1], vr[:, None, :])[0] < 1e-11
+
+
+def test_dense_unshared_equals_per_instance_shared():
+    rng = np.random.default_rng(7)
+    s, B = 5, 3
+    Ms, Ks = zip(*[workloads.random_dense_system(rng, s) for _ in range(B)])
+    Ms, Ks = np.array(Ms), np.array(Ks)
+    dt = np.array([0.01, 0.02, 0.015])
+    x0, v0 = rng.normal(size=(B, s)), rng.normal(size=(B, s))
+    _, _, xe, ve = oracle.dense("rk4", Ms, Ks, dt, x0, v0, 40, 0, shared=False)
+    for b in range(B):
+        _, _, xb, vb = oracle.dense("rk4", Ms[b], Ks[b], dt[b:b + 1], x0[b:b + 1], v0[b:b + 1], 40, 0)
+        np.testing.assert_array_equal(xe[b], xb[0])
+        np.testing.assert_array_equal(ve[b], vb[0])
+
+
+def test_chain_as_dense_agrees():
+    rng = np.random.default_rng(11)
+    s = 6
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    x0, v0 = rng.normal(size=(1, s)), np.zeros((1, s))
+    h = 1e-3
+    for method in ("rk4", "verlet"):
+        _, _, xc, vc = oracle.chain(method, m[None], k[None], [h], x0, v0, 500, 0)
+        _, _, xd, vd = oracle.dense(method, M, K, [h], x0, v0, 500, 0)
+        np.testing.assert_allclose(xc, xd, rtol=0, atol=1e-12 * np.abs(xc).max())
+        np.testing.assert_allclose(vc, vd, rtol=0, atol=1e-12 * np.abs(vc).max())
+
+
+# ------------------------------------------------------ A = M^-1 K ----------
+
+def test_form_a_solves_m_a_equals_k():
+    rng = np.random.default_rng(5)
+    for s in (1, 2, 9, 33):
+        M, K = workloads.random_dense_system(rng, s)
+        A = oracle.form_a(M, K)
+        np.testing.assert_allclose(M @ A, K, rtol=0, atol=1e-12 * np.abs(K).max())
+        np.testing.assert_allclose(A, np.linalg.solve(M, K), rtol=0, atol=1e-11 * np.abs(A).max())
+
+
+def test_form_a_rejects_non_spd():
+    M = np.array([[1.0, 2.0], [2.0, 1.0]])       # eigenvalues 3, -1
+    with pytest.raises(oracle.OracleError, match="status 2"):
+        oracle.form_a(M, np.eye(2))
+
+
+# ------------------------------------------------------ invariants ----------
+
+def test_verlet_shadow_invariant_conserved():
+    rng = np.random.default_rng(3)
+    s = 12
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    wmax = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    h = 0.3 / wmax
+    x0, v0 = rng.normal(size=(1, s)), rng.normal(size=(1, s)) * wmax
+    xf, vf, _, _ = oracle.chain("verlet", m[None], k[None], [h], x0, v0, 2000, 50)
+    Q = np.array([oracle.verlet_q_chain(m[None], k[None], [h], xf[f], vf[f])[0] for f in range(len(xf))])
+    E = np.array([oracle.energy_chain(m[None], k[None], xf[f], vf[f])[0] for f in range(len(xf))])
+    assert np.abs(Q / Q[0] - 1).max() < 1e-12
+    assert np.abs(E / E[0] - 1).max() > 1e-4       # plain E is not the conserved quantity
+
+
+def test_rk4_energy_decay_matches_amplification():
+    rng = np.random.default_rng(4)
+    s = 4
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    w, phi = cf.modes(M, K)
+    h = 0.6 / w[-1]
+    x0, v0 = rng.normal(size=s), rng.normal(size=s)
+    n = 400
+    _, _, xe, ve = oracle.chain("rk4", m[None], k[None], [h], x0[None], v0[None], n, 0)
+    E = oracle.energy_chain(m[None], k[None], xe, ve)[0]
+    q0, p0 = phi.T @ M @ x0, phi.T @ M @ v0
+    E_ref = 0.5 * np.sum((p0 ** 2 + (w * q0) ** 2) * cf.rk4_energy_factor(w * h) ** n)
+    assert E == pytest.approx(E_ref, rel=1e-12)
+    # the factor formula itself: |R(-i th)|^2
+    th = np.array([0.01, 0.1, 0.5, 1.0])
+    np.testing.assert_allclose(np.abs(cf.rk4_amplification(th)) ** 2, cf.rk4_energy_factor(th), rtol=1e-15)
+
+
+def test_energy_matches_quadratic_forms():
+    rng = np.random.default_rng(8)
+    s = 7
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    x, v = rng.normal(size=(2, s)), rng.normal(size=(2, s))
+    E = oracle.energy_chain(np.tile(m, (2, 1)), np.tile(k, (2, 1)), x, v)
+    Ed = oracle.energy_dense(M, K, x, v)
+    ref = 0.5 * np.einsum("bi,ij,bj->b", v, M, v) + 0.5 * np.einsum("bi,ij,bj->b", x, K, x)
+    np.testing.assert_allclose(E, ref, rtol=1e-13)
+    np.testing.assert_allclose(Ed, ref, rtol=1e-13)
+
+
+def test_verlet_time_reversal():
+    rng = np.random.default_rng(9)
+    s = 10
+    m, k = _random_chain(rng, s)
+    x0, v0 = rng.normal(size=(1, s)), rng.normal(size=(1, s))
+    h = 1e-3
+    _, _, x1, v1 = oracle.chain("verlet", m[None], k[None], [h], x0, v0, 1000, 0)
+    _, _, x2, v2 = oracle.chain("verlet", m[None], k[None], [-h], x1, v1, 1000, 0)
+    np.testing.assert_allclose(x2, x0, atol=1e-10)
+    np.testing.assert_allclose(v2, v0, atol=1e-8)
+
+
+def test_decoupled_springs_reduce_to_scalar_oscillator_and_free_mass():
+    """C2 = 0 in eq. (2): body 1 is a scalar oscillator, body 2 moves freely.
+    RK4 integrates uniform motion exactly, and body 1 follows R(-i w h)^n."""
+    m1, m2, c1 = 1.7, 0.9, 800.0
+    w = math.sqrt(c1 / m1)
+    h = 0.2 / w
+    x0, v0 = np.array([[0.3, -1.0]]), np.array([[2.0, 0.25]])
+    n = 123
+    _, _, xe, ve = oracle.chain("rk4", [[m1, m2]], [[c1, 0.0]], [h], x0, v0, n, 0)
+    assert xe[0, 1] == pytest.approx(-1.0 + 0.25 * n * h, rel=1e-14)
+    assert ve[0, 1] == 0.25
+    u = (w * 0.3 + 2.0j) * cf.rk4_amplification(w * h) ** n
+    assert xe[0, 0] == pytest.approx(u.real / w, rel=1e-12)
+    assert ve[0, 0] == pytest.approx(u.imag, rel=1e-12)
+
+
+def test_linearity():
+    rng = np.random.default_rng(12)
+    s = 5
+    m, k = _random_chain(rng, s)
+    xa, xb = rng.normal(size=(2, 1, s))
+    va, vb = rng.normal(size=(2, 1, s))
+    h = 2e-3
+    _, _, ea, fa = oracle.chain("rk4", m[None], k[None], [h], xa, va, 200, 0)
+    _, _, eb, fb = oracle.chain("rk4", m[None], k[None], [h], xb, vb, 200, 0)
+    _, _, ec, fc = oracle.chain("rk4", m[None], k[None], [h], 2 * xa - 3 * xb, 2 * va - 3 * vb, 200, 0)
+    np.testing.assert_allclose(ec, 2 * ea - 3 * eb, atol=1e-11)
+    np.testing.assert_allclose(fc, 2 * fa - 3 * fb, atol=1e-9)
+
+
+# ------------------------------------------------------ conventions --------
+
+def test_frames_and_zero_steps():
+    rng = np.random.default_rng(13)
+    m, k = _random_chain(rng, 3)
+    x0, v0 = rng.normal(size=(2, 3)), rng.normal(size=(2, 3))
+    mm, kk = np.tile(m, (2, 1)), np.tile(k, (2, 1))
+    xf, vf, xe, ve = oracle.chain("rk4", mm, kk, [1e-3, 2e-3], x0, v0, 10, 3)
+    assert xf.shape == (4, 2, 3)                   # frames at n = 0, 3, 6, 9
+    np.testing.assert_array_equal(xf[0], x0)
+    _, _, x9, _ = oracle.chain("rk4", mm, kk, [1e-3, 2e-3], x0, v0, 9, 0)
+    np.testing.assert_array_equal(xf[3], x9)
+    xf0, _, xe0, ve0 = oracle.chain("verlet", mm, kk, [1e-3, 2e-3], x0, v0, 0, 1)
+    np.testing.assert_array_equal(xe0, x0)
+    np.testing.assert_array_equal(ve0, v0)
+    assert xf0.shape == (1, 2, 3)
+
+
+def test_empty_batch():
+    xf, vf, xe, ve = oracle.chain("rk4", np.zeros((0, 4)), np.zeros((0, 4)), np.zeros(0),
+                                  np.zeros((0, 4)), np.zeros((0, 4)), 10, 2)
+    assert xe.shape == (0, 4) and xf.shape == (6, 0, 4)
+
+
+# ------------------------------------------- planted mistakes are caught -----
+
+MUTANTS = [
+    ("2.0 * k2x[i]", "1.0 * k2x[i]"),                       # wrong RK4 weight
+    ("x[i] + 0.5 * h * k2x[i]", "x[i] + 0.5 * h * k1x[i]"),  # wrong stage slope
+    ("f += k[i + 1] * (x[i + 1] - x[i])", "f -= k[i + 1] * (x[i + 1] - x[i])"),  # sign
+    ("(i == 0) ? x[0] : x[i] - x[i - 1]", "(i == 0) ? x[0] : x[i] - x[i]"),     # index
+    ("x[i] += h * v[i];         /* drift */", "x[i] += h * a[i];         /* drift */"),
+]
+
+
+@pytest.mark.parametrize("orig,mut", MUTANTS)
+def test_pins_catch_planted_oracle_mistakes(orig, mut, tmp_path):
+    """Recompile the oracle with one plausible mistake and check that the
+    discrete closed-form pin rejects it (CPU only)."""
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "osc_oracle.c")).read()
+    assert orig in src
+    mpath = tmp_path / "mut.c"
+    mpath.write_text(src.replace(orig, mut))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(mpath), "-lm"], check=True)
+    import ctypes
+    L = ctypes.CDLL(str(lib))
+    d = ctypes.POINTER(ctypes.c_double)
+    L.oracle_chain.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, d, d, d, d, d,
+                               ctypes.c_int64, ctypes.c_int64, d, d, d, d]
+    rng = np.random.default_rng(21)
+    s = 4
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    wmax = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    h = 0.3 / wmax
+    x0, v0 = rng.normal(size=s), rng.normal(size=s) * wmax
+    n = 50
+    bad = False
+    for meth, ref in ((0, cf.rk4_discrete), (1, cf.verlet_discrete)):
+        xe, ve = np.empty((1, s)), np.empty((1, s))
+        p = lambda a: np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(d)
+        args = [np.ascontiguousarray(a, dtype=np.float64) for a in (m[None], k[None], [h], x0[None], v0[None])]
+        L.oracle_chain(meth, 1, s, *[p(a) for a in args], n, 0, None, None, p(xe), p(ve))
+        xr, vr = ref([n], h, M, K, x0, v0)
+        err = max(oracle.rel_traj_err(xe, xr)[0], oracle.rel_traj_err(ve, vr)[0])
+        bad = bad or not (err < 1e-11)
+    assert bad, "planted mistake not detected"
