@@ -1,0 +1,166 @@
+/*
+ * osc.h -- C ABI of libosc, a gfx950 (MI355X) integrator for coupled linear
+ * oscillators.
+ *
+ * The systems are those of eq. (1) of Al-Oraiqat, "Parallel implementation
+ * of the coupled harmonic oscillator" (arXiv 1702.02207):
+ *     sum_j (m_ij x_j'' + k_ij x_j) = 0,   i.e.   x'' = -A x,  A = M^-1 K,
+ * reduced to the first-order system x' = v, v' = -A x (section 3) and advanced
+ * with a fixed step by classic four-stage Runge-Kutta (RK4) or by velocity
+ * Verlet.  Many independent instances are integrated at once.
+ *
+ * Two kinds of system are accepted:
+ *   OSC_CHAIN  the fixed-free spring chain of eq. (2) / Fig. 1 generalised to
+ *              s bodies: diagonal M (masses m_i) and tridiagonal K.  Spring 0
+ *              ties body 0 to the wall, spring i (i >= 1) joins bodies i-1 and
+ *              i, the last body is free.  s = 2 is exactly eq. (2) with
+ *              C1 = k[0], C2 = k[1].
+ *   OSC_DENSE  a general eq. (1) system: M symmetric positive definite and K
+ *              symmetric, both full s x s.  A = M^-1 K is formed on the GPU in
+ *              FP64 through the Cholesky factor of M.
+ *
+ * Conventions shared by every entry point
+ *   - All functions return an osc_status; no exception or abort crosses the
+ *     ABI.  On failure, osc_last_error() returns a thread-local message.
+ *   - State arrays are instance-major, row-major [batch][s].  Their element
+ *     type follows the precision: double for OSC_F64, float for OSC_F32.
+ *   - Frames are the states at steps n = 0, out_stride, 2*out_stride, ...
+ *     (n <= nsteps), stored [nframes][batch][s] with
+ *     nframes = nsteps / out_stride + 1; out_stride == 0 means no frames.
+ *     The time of frame f is t = f * out_stride * dt, formed in FP64 from
+ *     the integer step count.
+ *   - Device arrays are owned by the caller; the library never frees them and
+ *     keeps no pointer to them after the call's work has been enqueued.
+ *   - Work is enqueued on the stream given at creation (a hipStream_t; NULL
+ *     is the null stream).  osc_integrate and osc_energy are asynchronous:
+ *     they validate their arguments and return at once.  Errors found on the
+ *     device (a non-finite state) are reported by osc_sync.
+ *   - A handle may be used by one host thread at a time.
+ */
+#ifndef OSC_H
+#define OSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OSC_ABI_VERSION 1
+
+typedef enum {
+    OSC_OK = 0,
+    OSC_EINVAL = 1,      /* invalid argument (null pointer, size, enum, dt <= 0, ...) */
+    OSC_ENOTSPD = 2,     /* the Cholesky factorisation of M failed: M is not SPD */
+    OSC_EUNSTABLE = 3,   /* dt * omega_max lies outside the scheme's stability interval */
+    OSC_ENOMEM = 4,      /* device memory (or the configured HBM budget) exhausted */
+    OSC_EDEVICE = 5,     /* a HIP runtime call failed */
+    OSC_ENONFINITE = 6,  /* a state became NaN or infinite (reported by osc_sync) */
+    OSC_ENOTSUP = 7,     /* a combination this build does not provide */
+    OSC_ETIMEOUT = 8,    /* a wait ran out of time */
+    OSC_EBUSY = 9        /* the server is full / shutting down */
+} osc_status;
+
+typedef enum { OSC_CHAIN = 0, OSC_DENSE = 1 } osc_kind;
+typedef enum { OSC_RK4 = 0, OSC_VERLET = 1 } osc_method;
+typedef enum { OSC_F64 = 0, OSC_F32 = 1 } osc_prec;
+typedef enum { OSC_MEM_HOST = 0, OSC_MEM_DEVICE = 1 } osc_mem;
+
+/*
+ * Description of a batch of systems.
+ *
+ * OSC_CHAIN:  M = masses  [batch][s] (> 0),  K = springs [batch][s] (>= 0,
+ *             K[b][0] > 0 is the wall spring),  dt = [batch] (> 0).
+ * OSC_DENSE:  shared != 0: M, K are [s][s] row-major, used by every instance,
+ *             dt = [1];  shared == 0: M, K are [batch][s][s], dt = [batch].
+ * param_mem tells whether M, K and dt are host or device pointers.  They are
+ * read during osc_create only; the caller may free them afterwards.
+ *
+ * prec = OSC_F32 keeps the state in FP32 with compensated (two-term) updates
+ * and coefficients split into FP32 high + low parts; dense products run on
+ * MFMA with FP16 operands split into three terms (FP32 accumulation).
+ * prec = OSC_F64 runs everything in double.
+ */
+typedef struct osc_desc {
+    osc_kind kind;
+    osc_method method;
+    osc_prec prec;
+    int32_t s;            /* degrees of freedom per instance, >= 1 */
+    int64_t batch;        /* number of instances, >= 0 (0: every call is a no-op) */
+    int32_t shared;       /* dense only */
+    osc_mem param_mem;
+    const double *M;
+    const double *K;
+    const double *dt;
+} osc_desc;
+
+typedef struct osc_sys osc_sys;
+
+/*
+ * osc_create -- validate a description and prepare the device-side system
+ * (eq. (1)): for chains, the per-body coefficients of A = M^-1 K scaled by
+ * dt^2; for dense systems, A = M^-1 K by FP64 Cholesky and its scaled split
+ * operands.  Checks positive definiteness (OSC_ENOTSPD) and stability: the
+ * step is rejected (OSC_EUNSTABLE) when dt * omega_bound exceeds 2.78 for
+ * RK4 (the imaginary-axis limit is 2*sqrt(2)) or 1.99 for Verlet (limit 2),
+ * with omega_bound a Gershgorin bound (chains) or a power-iteration estimate
+ * with a 2 % margin (dense).  Blocks until the preparation has finished.
+ * stream: hipStream_t or NULL.  *out receives a new handle on success.
+ */
+osc_status osc_create(const osc_desc *desc, void *stream, osc_sys **out);
+
+/*
+ * osc_integrate -- advance every instance nsteps steps from (x0, v0).
+ * x0, v0:            device [batch][s] initial state (read only).
+ * x_frames, v_frames: device [nframes][batch][s] or NULL to skip.
+ * x_end, v_end:      device [batch][s] final state, or NULL to skip.
+ * nsteps = 0 copies the initial state out.  Asynchronous on the handle's
+ * stream.  The result of an instance does not depend on the batch it sits
+ * in or on the launch configuration chosen.
+ */
+osc_status osc_integrate(osc_sys *sys, const void *x0, const void *v0, int64_t nsteps,
+                         int64_t out_stride, void *x_frames, void *v_frames, void *x_end,
+                         void *v_end);
+
+/*
+ * osc_integrate_plain -- the same result as osc_integrate with no frames,
+ * computed the plain way: one instance at a time and one time step per kernel
+ * launch, with the state kept in device memory between launches.  It exists
+ * as the per-instance baseline that the batched path is measured against.
+ */
+osc_status osc_integrate_plain(osc_sys *sys, const void *x0, const void *v0, int64_t nsteps,
+                               void *x_end, void *v_end);
+
+/*
+ * osc_energy -- E[b] = 1/2 v^T M v + 1/2 x^T K x for every instance, in FP64
+ * on the device (chain: 1/2 sum m_i v_i^2 + 1/2 sum k_i (x_i - x_{i-1})^2).
+ * x, v: device [batch][s] in the handle's precision; E: device double [batch].
+ */
+osc_status osc_energy(osc_sys *sys, const void *x, const void *v, double *E);
+
+/*
+ * osc_shadow_energy -- the quantity velocity Verlet conserves exactly:
+ * Q[b] = v^T M v + x^T K x - (dt^2/4) (K x)^T M^-1 (K x), FP64 on the device.
+ * Same arguments as osc_energy.
+ */
+osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double *Q);
+
+/* osc_sync -- wait for the handle's stream; returns OSC_ENONFINITE if any
+ * integration since the last osc_sync produced a non-finite state. */
+osc_status osc_sync(osc_sys *sys);
+
+/* osc_destroy -- release the handle (waits for its queued work).  NULL is a no-op. */
+void osc_destroy(osc_sys *sys);
+
+/* osc_last_error -- description of the last failure on this thread ("" if none). */
+const char *osc_last_error(void);
+
+/* osc_abi_version -- OSC_ABI_VERSION of the loaded library. */
+int osc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSC_H */

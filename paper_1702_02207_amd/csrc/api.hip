@@ -1,0 +1,275 @@
+// Host runtime behind the C ABI declared in include/osc.h.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+
+#include "osc_internal.h"
+
+namespace osc {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Stability limits on the imaginary axis with a small margin: RK4 is stable
+// for h omega <= 2 sqrt(2) = 2.828, velocity Verlet for h omega < 2.
+constexpr double kRk4Limit = 2.78;
+constexpr double kVerletLimit = 1.99;
+
+size_t elem_size(osc_prec p) { return p == OSC_F64 ? sizeof(double) : sizeof(float); }
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { pool_free(p); }
+    void *release() {
+        void *r = p;
+        p = nullptr;
+        return r;
+    }
+};
+
+osc_status copy_in(void *dst, const void *src, size_t bytes, osc_mem where, hipStream_t st) {
+    OSC_HIP(hipMemcpyAsync(dst, src, bytes, where == OSC_MEM_HOST ? hipMemcpyHostToDevice
+                                                                  : hipMemcpyDeviceToDevice, st));
+    return OSC_OK;
+}
+
+void release(osc_sys *s) {
+    if (!s) return;
+    pool_free(s->m);
+    pool_free(s->k);
+    pool_free(s->h);
+    pool_free(s->coef);
+    pool_free(s->flag);
+    pool_free(s->plain_state);
+    delete s;
+}
+
+template <typename T>
+ChainCoef<T> coef_of(const osc_sys *s) {
+    const size_t n = (size_t)s->batch * s->s;
+    T *base = static_cast<T *>(s->coef);
+    ChainCoef<T> c;
+    c.clh = base;
+    c.crh = base + n;
+    c.cll = std::is_same<T, float>::value ? base + 2 * n : nullptr;
+    c.crl = std::is_same<T, float>::value ? base + 3 * n : nullptr;
+    c.h = s->h;
+    return c;
+}
+
+template <typename T>
+osc_status create_chain(osc_sys *s, const osc_desc *d) {
+    const size_t n = (size_t)s->batch * s->s;
+    const hipStream_t st = s->stream;
+    s->m = static_cast<double *>(pool_alloc(n * sizeof(double)));
+    s->k = static_cast<double *>(pool_alloc(n * sizeof(double)));
+    s->h = static_cast<double *>(pool_alloc((size_t)s->batch * sizeof(double)));
+    const int planes = std::is_same<T, float>::value ? 4 : 2;
+    s->coef = pool_alloc(planes * n * sizeof(T));
+    // scratch: [theta bound (double)][bad flag (int)]
+    s->flag = static_cast<int *>(pool_alloc(64));
+    DevBuf scratch;
+    scratch.p = pool_alloc(64);
+    if (!s->m || !s->k || !s->h || !s->coef || !s->flag || !scratch.p)
+        return fail(OSC_ENOMEM, "device memory / HBM budget exhausted in osc_create");
+    osc_status r;
+    if ((r = copy_in(s->m, d->M, n * sizeof(double), d->param_mem, st))) return r;
+    if ((r = copy_in(s->k, d->K, n * sizeof(double), d->param_mem, st))) return r;
+    // dt goes straight to the per-instance step buffer h.
+    if ((r = copy_in(s->h, d->dt, (size_t)s->batch * sizeof(double), d->param_mem, st))) return r;
+    OSC_HIP(hipMemsetAsync(s->flag, 0, 64, st));
+    OSC_HIP(hipMemsetAsync(scratch.p, 0, 64, st));
+    double *theta = static_cast<double *>(scratch.p);
+    int *bad = reinterpret_cast<int *>(static_cast<char *>(scratch.p) + 8);
+    T *base = static_cast<T *>(s->coef);
+    r = chain_prepare<T>(s->batch, s->s, s->m, s->k, s->h, base, base + n,
+                         planes == 4 ? base + 2 * n : nullptr, planes == 4 ? base + 3 * n : nullptr,
+                         /*hout=*/nullptr, theta, bad, st);
+    if (r) return r;
+    struct {
+        double theta;
+        int bad;
+        int pad;
+    } host{};
+    OSC_HIP(hipMemcpyAsync(&host, scratch.p, 16, hipMemcpyDeviceToHost, st));
+    OSC_HIP(hipStreamSynchronize(st));
+    if (host.bad) return fail(OSC_EINVAL, "chain parameters need m > 0, k >= 0 and finite dt > 0");
+    s->theta_max = host.theta;
+    const double lim = s->method == OSC_RK4 ? kRk4Limit : kVerletLimit;
+    if (!(host.theta <= lim))
+        return fail(OSC_EUNSTABLE, "dt * omega bound " + std::to_string(host.theta) + " exceeds " +
+                                       std::to_string(lim));
+    s->cfg = chain_pick_config(s->s);
+    return OSC_OK;
+}
+
+template <typename T>
+osc_status integrate_chain(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                           void *xf, void *vf, void *xe, void *ve) {
+    ChainLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.c = coef_of<T>(s);
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.state = nullptr;
+    a.nsteps = nsteps;
+    a.n0 = 0;
+    a.out_stride = out_stride;
+    a.xf = static_cast<T *>(xf);
+    a.vf = static_cast<T *>(vf);
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.nonfinite = s->flag;
+    a.load_mode = LOAD_USER;
+    a.store_mode = STORE_USER;
+    return chain_launch<T>(a, s->method, s->cfg, s->stream);
+}
+
+template <typename T>
+osc_status plain_chain(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, void *xe, void *ve) {
+    const size_t n = (size_t)s->batch * s->s;
+    if (!s->plain_state) {
+        s->plain_state = pool_alloc(4 * n * sizeof(T));
+        if (!s->plain_state) return fail(OSC_ENOMEM, "device memory exhausted in osc_integrate_plain");
+    }
+    ChainLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.c = coef_of<T>(s);
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.state = static_cast<T *>(s->plain_state);
+    a.nsteps = nsteps;
+    a.n0 = 0;
+    a.out_stride = 0;
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.nonfinite = s->flag;
+    return chain_plain<T>(a, s->method, s->stream);
+}
+
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+osc_status fail(osc_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+}  // namespace osc
+
+using namespace osc;
+
+extern "C" {
+
+int osc_abi_version(void) { return OSC_ABI_VERSION; }
+
+const char *osc_last_error(void) { return g_last_error.c_str(); }
+
+osc_status osc_create(const osc_desc *d, void *stream, osc_sys **out) {
+    g_last_error.clear();
+    if (!out) return fail(OSC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(OSC_EINVAL, "desc is NULL");
+    if (d->kind != OSC_CHAIN && d->kind != OSC_DENSE) return fail(OSC_EINVAL, "unknown kind");
+    if (d->method != OSC_RK4 && d->method != OSC_VERLET) return fail(OSC_EINVAL, "unknown method");
+    if (d->prec != OSC_F64 && d->prec != OSC_F32) return fail(OSC_EINVAL, "unknown precision");
+    if (d->param_mem != OSC_MEM_HOST && d->param_mem != OSC_MEM_DEVICE)
+        return fail(OSC_EINVAL, "unknown param_mem");
+    if (d->s < 1) return fail(OSC_EINVAL, "s must be >= 1");
+    if (d->batch < 0) return fail(OSC_EINVAL, "batch must be >= 0");
+    if (!d->M || !d->K || !d->dt) return fail(OSC_EINVAL, "M, K and dt must be non-NULL");
+    if ((double)d->batch * d->s > 4.0e9) return fail(OSC_EINVAL, "batch * s too large");
+    if (d->kind == OSC_DENSE) return fail(OSC_ENOTSUP, "dense systems are not available in this build");
+    if (d->kind == OSC_CHAIN && d->s > 2048) return fail(OSC_ENOTSUP, "chains support s <= 2048");
+
+    osc_sys *s = new (std::nothrow) osc_sys();
+    if (!s) return fail(OSC_ENOMEM, "host allocation failed");
+    s->kind = d->kind;
+    s->method = d->method;
+    s->prec = d->prec;
+    s->s = d->s;
+    s->batch = d->batch;
+    s->shared = d->shared;
+    s->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(OSC_EDEVICE, "no HIP device");
+    }
+    osc_status r = d->prec == OSC_F32 ? create_chain<float>(s, d) : create_chain<double>(s, d);
+    if (r != OSC_OK) {
+        (void)hipStreamSynchronize(s->stream);
+        release(s);
+        return r;
+    }
+    *out = s;
+    return OSC_OK;
+}
+
+osc_status osc_integrate(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                         void *xf, void *vf, void *xe, void *ve) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
+    if (s->batch == 0) return OSC_OK;
+    if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
+    if (out_stride < 0) return fail(OSC_EINVAL, "out_stride must be >= 0");
+    if (out_stride == 0 && (xf || vf)) return fail(OSC_EINVAL, "frames requested with out_stride == 0");
+    return s->prec == OSC_F32 ? integrate_chain<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
+                              : integrate_chain<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
+}
+
+osc_status osc_integrate_plain(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, void *xe, void *ve) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
+    if (s->batch == 0) return OSC_OK;
+    if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
+    return s->prec == OSC_F32 ? plain_chain<float>(s, x0, v0, nsteps, xe, ve)
+                              : plain_chain<double>(s, x0, v0, nsteps, xe, ve);
+}
+
+static osc_status energy_common(osc_sys *s, const void *x, const void *v, double *E, bool shadow) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    if (s->batch == 0) return OSC_OK;
+    if (!x || !v || !E) return fail(OSC_EINVAL, "x, v and E must be non-NULL");
+    if (s->prec == OSC_F32)
+        return chain_energy<float>(s->batch, s->s, s->m, s->k, s->h, static_cast<const float *>(x),
+                                   static_cast<const float *>(v), E, shadow, s->stream);
+    return chain_energy<double>(s->batch, s->s, s->m, s->k, s->h, static_cast<const double *>(x),
+                                static_cast<const double *>(v), E, shadow, s->stream);
+}
+
+osc_status osc_energy(osc_sys *s, const void *x, const void *v, double *E) {
+    return energy_common(s, x, v, E, false);
+}
+
+osc_status osc_shadow_energy(osc_sys *s, const void *x, const void *v, double *Q) {
+    return energy_common(s, x, v, Q, true);
+}
+
+osc_status osc_sync(osc_sys *s) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    OSC_HIP(hipStreamSynchronize(s->stream));
+    int flag = 0;
+    OSC_HIP(hipMemcpy(&flag, s->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        OSC_HIP(hipMemset(s->flag, 0, sizeof(int)));
+        return fail(OSC_ENONFINITE, "a state became non-finite");
+    }
+    return OSC_OK;
+}
+
+void osc_destroy(osc_sys *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    release(s);
+}
+
+}  // extern "C"

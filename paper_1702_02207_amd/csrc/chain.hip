@@ -1,0 +1,491 @@
+// Batched integration of fixed-free spring chains (eq. (2) generalised to s
+// bodies; s = 2 is the two-mass system itself) on gfx950.
+//
+// Layout.  A group of LPI consecutive lanes of one 64-wide wavefront holds
+// one instance; each lane keeps DPL consecutive degrees of freedom of that
+// instance in registers for the whole launch.  LPI = 1 is the
+// instance-per-lane layout (2-DOF ensembles), LPI = 64 one instance per
+// wavefront (long chains).  The only cross-lane traffic of the tridiagonal
+// stencil is the edge value of each neighbouring lane, fetched with DPP
+// whole-wave shifts (wave_shr:1 / wave_shl:1), so no LDS and no barrier is
+// used.  Many time steps run per launch; HBM is touched only to load the
+// coefficients and state, to write frames and to store the final state.
+//
+// Arithmetic (scaled time tau = t/h, w = h v, B = h^2 A):
+//   RK4.  For a linear autonomous system the classic four-stage RK4 map is
+//   exactly the degree-4 Taylor polynomial of exp(hL), L = [[0, I], [-A, 0]]
+//   (section 3's first-order form).  With P = Bx, Q = Bw, P2 = BP, Q2 = BQ:
+//     dx = w - P/2 - Q/6 + P2/24,   dw = -P - Q/2 + P2/6 + Q2/24.
+//   The stage form and this form differ only in rounding; this one keeps the
+//   inexact constants 1/6 and 1/24 off the dominant terms.
+//   Verlet.  Velocity Verlet written as leapfrog on the half-step velocity:
+//     x_{n+1} = x_n + w_{n+1/2},  w_{n+3/2} = w_{n+1/2} - B x_{n+1},
+//   with w_{1/2} = w_0 - B x_0 / 2 and w_n = w_{n+1/2} + B x_n / 2 at output.
+//
+// FP32 precision scheme: x and w are kept as an unevaluated sum hi + lo
+// (compensated / Kahan update), and B x uses coefficients split into FP32
+// hi + lo parts; the products with w, B x and B w, which enter the update
+// multiplied by at least one more power of the small step, use hi only.
+// FP64 runs the same code without the low parts.
+
+#include <type_traits>
+
+#include "osc_internal.h"
+
+namespace osc {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_fmaf(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
+// Whole-wave DPP shifts: lane i receives lane i-1 (from_left) or lane i+1
+// (from_right); lanes shifted in from outside the wave receive 0.
+__device__ __forceinline__ int shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+
+__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, shr1(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, shl1(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double from_left(double v) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    unsigned lo = (unsigned)shr1((int)(unsigned)b), hi = (unsigned)shr1((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    unsigned lo = (unsigned)shl1((int)(unsigned)b), hi = (unsigned)shl1((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T, int DPL, int LPI>
+struct Group {
+    bool first, last;   // lane is the first / last of its instance's group
+
+    // Neighbouring values across the lane boundary: the last DOF of the left
+    // lane and the first DOF of the right lane.  Outside the chain the wall
+    // (left) is at rest; the free end (right) has a zero coefficient, the 0
+    // only keeps the product finite.
+    __device__ __forceinline__ void halo(const T (&u)[DPL], T &prev, T &next) const {
+        if constexpr (LPI == 1) {
+            prev = T(0);
+            next = T(0);
+        } else {
+            T p = from_left(u[DPL - 1]);
+            T n = from_right(u[0]);
+            prev = first ? T(0) : p;
+            next = last ? T(0) : n;
+        }
+    }
+
+    // out = B u with one coefficient set: (B u)_j = cl_j e_j - cr_j e_{j+1},
+    // e_j = u_j - u_{j-1} the extension of spring j.
+    __device__ __forceinline__ void apply(const T (&u)[DPL], const T (&cl)[DPL], const T (&cr)[DPL],
+                                          T (&out)[DPL]) const {
+        T prev, next;
+        halo(u, prev, next);
+        T el = u[0] - prev;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const T un = (j + 1 < DPL) ? u[(j + 1 < DPL) ? j + 1 : j] : next;
+            const T er = un - u[j];
+            out[j] = fmat(cl[j], el, -cr[j] * er);
+            el = er;
+        }
+    }
+
+    // out = B u with split coefficients (hi + lo), the low products first.
+    __device__ __forceinline__ void apply2(const T (&u)[DPL], const T (&clh)[DPL], const T (&crh)[DPL],
+                                           const T (&cll)[DPL], const T (&crl)[DPL],
+                                           T (&out)[DPL]) const {
+        T prev, next;
+        halo(u, prev, next);
+        T el = u[0] - prev;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const T un = (j + 1 < DPL) ? u[(j + 1 < DPL) ? j + 1 : j] : next;
+            const T er = un - u[j];
+            out[j] = fmat(clh[j], el, fmat(-crh[j], er, fmat(cll[j], el, -crl[j] * er)));
+            el = er;
+        }
+    }
+};
+
+// hi + lo <- hi + lo + y (compensated summation); FP64 adds directly.
+template <typename T>
+__device__ __forceinline__ void comp_add(T &hi, T &lo, T y) {
+    if constexpr (std::is_same<T, float>::value) {
+        y = y + lo;
+        const T t = hi + y;
+        lo = y - (t - hi);
+        hi = t;
+    } else {
+        hi = hi + y;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ bool finite(T v) { return __builtin_isfinite(v); }
+
+template <typename T, int DPL, int LPI, int METHOD>
+__global__ void __launch_bounds__(256) chain_kernel(ChainLaunch<T> a) {
+    constexpr bool COMP = std::is_same<T, float>::value;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = g / LPI;
+    const int sl = (int)(g % LPI);
+    const bool active = b < a.batch;
+    const int s = a.s;
+    const int d0 = sl * DPL;
+    Group<T, DPL, LPI> grp{sl == 0, sl == LPI - 1};
+
+    T clh[DPL], crh[DPL], cll[DPL], crl[DPL];
+    T x[DPL], xl[DPL], w[DPL], wl[DPL];
+    const size_t base = (size_t)(active ? b : 0) * s;
+    const double h = active ? a.c.h[b] : 1.0;
+    const size_t plane = (size_t)a.batch * s;
+
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int d = d0 + j;
+        const bool v = active && d < s;
+        const size_t i = base + d;
+        clh[j] = v ? a.c.clh[i] : T(0);
+        crh[j] = v ? a.c.crh[i] : T(0);
+        if constexpr (COMP) {
+            cll[j] = v ? a.c.cll[i] : T(0);
+            crl[j] = v ? a.c.crl[i] : T(0);
+        } else {
+            cll[j] = T(0);
+            crl[j] = T(0);
+        }
+        if (a.load_mode == LOAD_USER) {
+            x[j] = v ? a.x0[i] : T(0);
+            xl[j] = T(0);
+            const double wd = v ? h * (double)a.v0[i] : 0.0;
+            w[j] = (T)wd;
+            wl[j] = COMP ? (T)(wd - (double)w[j]) : T(0);
+        } else {
+            x[j] = v ? a.state[i] : T(0);
+            xl[j] = v ? a.state[plane + i] : T(0);
+            w[j] = v ? a.state[2 * plane + i] : T(0);
+            wl[j] = v ? a.state[3 * plane + i] : T(0);
+        }
+    }
+
+    const double invh = 1.0 / h;
+    T P[DPL];   // Verlet: B x at the current full step
+    if constexpr (METHOD == OSC_VERLET) {
+        if constexpr (COMP) grp.apply2(x, clh, crh, cll, crl, P);
+        else grp.apply(x, clh, crh, P);
+        if (a.load_mode == LOAD_USER) {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) comp_add(w[j], wl[j], T(-0.5) * P[j]);   // w_{1/2}
+        }
+    }
+
+    // velocity at the current full step, in FP64 before the final rounding
+    auto vel = [&](int j) -> double {
+        double wv = (double)w[j] + (double)wl[j];
+        if constexpr (METHOD == OSC_VERLET) wv += 0.5 * (double)P[j];
+        return wv * invh;
+    };
+    // the caller's initial state is copied out unchanged (frame 0, nsteps = 0)
+    const bool untouched = a.load_mode == LOAD_USER;
+    auto write_frame = [&](int64_t f, bool initial) {
+        const size_t fo = (size_t)f * plane;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int d = d0 + j;
+            if (active && d < s) {
+                if (a.xf) a.xf[fo + base + d] = initial ? a.x0[base + d] : (T)((double)x[j] + (double)xl[j]);
+                if (a.vf) a.vf[fo + base + d] = initial ? a.v0[base + d] : (T)vel(j);
+            }
+        }
+    };
+
+    int64_t n = a.n0;
+    const int64_t nend = a.n0 + a.nsteps;
+    const int64_t stride = a.out_stride;
+    if (stride > 0 && untouched && n % stride == 0) write_frame(n / stride, true);
+
+    while (n < nend) {
+        int64_t stop = nend;
+        if (stride > 0) {
+            const int64_t nf = (n / stride + 1) * stride;
+            stop = nf < stop ? nf : stop;
+        }
+        for (int64_t it = n; it < stop; ++it) {
+            if constexpr (METHOD == OSC_RK4) {
+                T Q[DPL];
+                if constexpr (COMP) grp.apply2(x, clh, crh, cll, crl, P);
+                else grp.apply(x, clh, crh, P);
+                grp.apply(w, clh, crh, Q);
+                // P2 = B P and Q2 = B Q, formed per DOF as they are consumed
+                T pprev, pnext, qprev, qnext;
+                grp.halo(P, pprev, pnext);
+                grp.halo(Q, qprev, qnext);
+                T epl = P[0] - pprev, eql = Q[0] - qprev;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const T pn = (j + 1 < DPL) ? P[(j + 1 < DPL) ? j + 1 : j] : pnext;
+                    const T qn = (j + 1 < DPL) ? Q[(j + 1 < DPL) ? j + 1 : j] : qnext;
+                    const T epr = pn - P[j], eqr = qn - Q[j];
+                    const T P2 = fmat(clh[j], epl, -crh[j] * epr);
+                    const T Q2 = fmat(clh[j], eql, -crh[j] * eqr);
+                    epl = epr;
+                    eql = eqr;
+                    const T yx = fmat(T(1.0 / 24.0), P2, fmat(T(-1.0 / 6.0), Q[j], fmat(T(-0.5), P[j], w[j])));
+                    const T yw = fmat(T(1.0 / 24.0), Q2, fmat(T(1.0 / 6.0), P2, fmat(T(-0.5), Q[j], -P[j])));
+                    comp_add(x[j], xl[j], yx);
+                    comp_add(w[j], wl[j], yw);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) comp_add(x[j], xl[j], w[j]);
+                if constexpr (COMP) grp.apply2(x, clh, crh, cll, crl, P);
+                else grp.apply(x, clh, crh, P);
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) comp_add(w[j], wl[j], -P[j]);
+            }
+        }
+        n = stop;
+        if (stride > 0 && n % stride == 0) write_frame(n / stride, false);
+    }
+    const bool copy_input = untouched && a.nsteps == 0;
+
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int d = d0 + j;
+        if (!(active && d < s)) continue;
+        const size_t i = base + d;
+        ok = ok && finite(x[j]) && finite(w[j]);
+        if (a.store_mode & STORE_STATE) {
+            a.state[i] = x[j];
+            a.state[plane + i] = xl[j];
+            a.state[2 * plane + i] = w[j];
+            a.state[3 * plane + i] = wl[j];
+        }
+        if (a.store_mode & STORE_USER) {
+            if (a.xe) a.xe[i] = copy_input ? a.x0[i] : (T)((double)x[j] + (double)xl[j]);
+            if (a.ve) a.ve[i] = copy_input ? a.v0[i] : (T)vel(j);
+        }
+    }
+    if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
+}
+
+// --------------------------------------------------------------------------
+// configuration table
+// --------------------------------------------------------------------------
+struct Entry {
+    int lpi, dpl;
+};
+constexpr Entry kConfigs[] = {
+    {1, 1}, {1, 2}, {1, 3}, {1, 4}, {1, 5}, {1, 6}, {1, 7}, {1, 8},
+    {2, 8}, {4, 8}, {8, 8}, {16, 8}, {32, 8},
+    {64, 4}, {64, 8}, {64, 16}, {64, 32},
+};
+constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
+
+template <typename T, int METHOD>
+using KernelFn = void (*)(ChainLaunch<T>);
+
+template <typename T, int METHOD, int I>
+constexpr KernelFn<T, METHOD> kernel_at() {
+    return &chain_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD>;
+}
+
+template <typename T, int METHOD, int... I>
+constexpr auto make_table(std::integer_sequence<int, I...>) {
+    struct Table {
+        KernelFn<T, METHOD> f[sizeof...(I)];
+    };
+    return Table{{kernel_at<T, METHOD, I>()...}};
+}
+
+template <typename T, int METHOD>
+KernelFn<T, METHOD> lookup(ChainConfig cfg) {
+    static const auto table = make_table<T, METHOD>(std::make_integer_sequence<int, kNumConfigs>{});
+    for (int i = 0; i < kNumConfigs; ++i)
+        if (kConfigs[i].lpi == cfg.lpi && kConfigs[i].dpl == cfg.dpl) return table.f[i];
+    return nullptr;
+}
+
+}  // namespace
+
+int chain_num_configs() { return kNumConfigs; }
+ChainConfig chain_config_at(int i) { return ChainConfig{kConfigs[i].lpi, kConfigs[i].dpl}; }
+
+ChainConfig chain_pick_config(int s) {
+    if (s <= 8) return ChainConfig{1, s};
+    // smallest capacity >= s; among equal capacity prefer more DOFs per lane
+    ChainConfig best{0, 0};
+    long best_cap = 0;
+    for (int i = 0; i < kNumConfigs; ++i) {
+        const long cap = (long)kConfigs[i].lpi * kConfigs[i].dpl;
+        if (cap < s || kConfigs[i].lpi == 1) continue;
+        if (best.lpi == 0 || cap < best_cap || (cap == best_cap && kConfigs[i].dpl > best.dpl)) {
+            best = ChainConfig{kConfigs[i].lpi, kConfigs[i].dpl};
+            best_cap = cap;
+        }
+    }
+    return best;
+}
+
+template <typename T>
+osc_status chain_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, hipStream_t st) {
+    if ((long)cfg.lpi * cfg.dpl < a.s)
+        return fail(OSC_EINVAL, "chain configuration too small for s");
+    if (a.batch == 0) return OSC_OK;
+    const int64_t threads = a.batch * cfg.lpi;
+    const int64_t blocks = (threads + 255) / 256;
+    if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "batch too large for one launch");
+    if (method == OSC_RK4) {
+        auto f = lookup<T, OSC_RK4>(cfg);
+        if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    } else {
+        auto f = lookup<T, OSC_VERLET>(cfg);
+        if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    }
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+template osc_status chain_launch<float>(const ChainLaunch<float> &, int, ChainConfig, hipStream_t);
+template osc_status chain_launch<double>(const ChainLaunch<double> &, int, ChainConfig, hipStream_t);
+
+// --------------------------------------------------------------------------
+// plain baseline: one instance, one step per launch, state in device memory
+// --------------------------------------------------------------------------
+namespace {
+
+constexpr int kPlainThreads = 1024;
+constexpr int kPlainMaxS = 2048;
+
+// One time step of one instance.  Thread t owns DOFs t, t + 1024, ...;
+// neighbours are exchanged through LDS.
+template <typename T, int METHOD>
+__global__ void __launch_bounds__(kPlainThreads) chain_plain_step(ChainLaunch<T> a, int64_t b) {
+    constexpr bool COMP = std::is_same<T, float>::value;
+    __shared__ T su[kPlainMaxS + 2];
+    __shared__ T sv[kPlainMaxS + 2];
+    const int s = a.s;
+    const size_t plane = (size_t)a.batch * s;
+    const size_t base = (size_t)b * s;
+    T *X = a.state, *XL = a.state + plane, *W = a.state + 2 * plane, *WL = a.state + 3 * plane;
+
+    auto coef = [&](int d, T &ch, T &rh, T &cl, T &rl) {
+        ch = a.c.clh[base + d];
+        rh = a.c.crh[base + d];
+        cl = COMP ? a.c.cll[base + d] : T(0);
+        rl = COMP ? a.c.crl[base + d] : T(0);
+    };
+    // (B u)_d from an LDS copy of u with su[0] = 0 (wall) and su[s+1] = 0
+    auto bop = [&](const T *u, int d, T ch, T rh, T cl, T rl, bool lo) -> T {
+        const T el = u[d + 1] - u[d];
+        const T er = u[d + 2] - u[d + 1];
+        if (lo) return fmat(ch, el, fmat(-rh, er, fmat(cl, el, -rl * er)));
+        return fmat(ch, el, -rh * er);
+    };
+
+    if (threadIdx.x == 0) {
+        su[0] = T(0);
+        sv[0] = T(0);
+        su[s + 1] = T(0);
+        sv[s + 1] = T(0);
+    }
+    if constexpr (METHOD == OSC_RK4) {
+        for (int d = threadIdx.x; d < s; d += kPlainThreads) {
+            su[d + 1] = X[base + d];
+            sv[d + 1] = W[base + d];
+        }
+        __syncthreads();
+        T P[kPlainMaxS / kPlainThreads], Q[kPlainMaxS / kPlainThreads];
+        int q = 0;
+        for (int d = threadIdx.x; d < s; d += kPlainThreads, ++q) {
+            T ch, rh, cl, rl;
+            coef(d, ch, rh, cl, rl);
+            P[q] = bop(su, d, ch, rh, cl, rl, COMP);
+            Q[q] = bop(sv, d, ch, rh, cl, rl, false);
+        }
+        __syncthreads();
+        q = 0;
+        for (int d = threadIdx.x; d < s; d += kPlainThreads, ++q) {
+            su[d + 1] = P[q];
+            sv[d + 1] = Q[q];
+        }
+        __syncthreads();
+        q = 0;
+        for (int d = threadIdx.x; d < s; d += kPlainThreads, ++q) {
+            T ch, rh, cl, rl;
+            coef(d, ch, rh, cl, rl);
+            const T P2 = bop(su, d, ch, rh, cl, rl, false);
+            const T Q2 = bop(sv, d, ch, rh, cl, rl, false);
+            T x = X[base + d], xl = XL[base + d], w = W[base + d], wl = WL[base + d];
+            const T yx = fmat(T(1.0 / 24.0), P2, fmat(T(-1.0 / 6.0), Q[q], fmat(T(-0.5), P[q], w)));
+            const T yw = fmat(T(1.0 / 24.0), Q2, fmat(T(1.0 / 6.0), P2, fmat(T(-0.5), Q[q], -P[q])));
+            comp_add(x, xl, yx);
+            comp_add(w, wl, yw);
+            X[base + d] = x;
+            XL[base + d] = xl;
+            W[base + d] = w;
+            WL[base + d] = wl;
+        }
+    } else {
+        for (int d = threadIdx.x; d < s; d += kPlainThreads) {
+            T x = X[base + d], xl = XL[base + d];
+            comp_add(x, xl, W[base + d]);
+            X[base + d] = x;
+            XL[base + d] = xl;
+            su[d + 1] = x;
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < s; d += kPlainThreads) {
+            T ch, rh, cl, rl;
+            coef(d, ch, rh, cl, rl);
+            const T P = bop(su, d, ch, rh, cl, rl, COMP);
+            T w = W[base + d], wl = WL[base + d];
+            comp_add(w, wl, -P);
+            W[base + d] = w;
+            WL[base + d] = wl;
+        }
+    }
+}
+
+}  // namespace
+
+template <typename T>
+osc_status chain_plain(const ChainLaunch<T> &a, int method, hipStream_t st) {
+    if (a.s > kPlainMaxS) return fail(OSC_ENOTSUP, "plain integrator supports s <= 2048");
+    // convert the user state, run single steps, convert back
+    ChainLaunch<T> conv = a;
+    conv.nsteps = 0;
+    conv.out_stride = 0;
+    conv.load_mode = LOAD_USER;
+    conv.store_mode = STORE_STATE;
+    const ChainConfig cfg = chain_pick_config(a.s);
+    osc_status r = chain_launch<T>(conv, method, cfg, st);
+    if (r != OSC_OK) return r;
+    const int threads = a.s < kPlainThreads ? ((a.s + 63) / 64) * 64 : kPlainThreads;
+    for (int64_t b = 0; b < a.batch; ++b) {
+        for (int64_t n = 0; n < a.nsteps; ++n) {
+            if (method == OSC_RK4)
+                hipLaunchKernelGGL((chain_plain_step<T, OSC_RK4>), dim3(1), dim3(threads), 0, st, a, b);
+            else
+                hipLaunchKernelGGL((chain_plain_step<T, OSC_VERLET>), dim3(1), dim3(threads), 0, st, a, b);
+        }
+        OSC_HIP(hipGetLastError());
+    }
+    conv.load_mode = LOAD_STATE;
+    conv.store_mode = STORE_USER;
+    conv.n0 = a.nsteps;
+    return chain_launch<T>(conv, method, cfg, st);
+}
+
+template osc_status chain_plain<float>(const ChainLaunch<float> &, int, hipStream_t);
+template osc_status chain_plain<double>(const ChainLaunch<double> &, int, hipStream_t);
+
+}  // namespace osc

@@ -1,0 +1,126 @@
+// Internal declarations of libosc (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "osc.h"
+
+namespace osc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+osc_status fail(osc_status st, const std::string &msg);
+#define OSC_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::osc::fail(OSC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory pool with an HBM budget (pool.cpp)
+// ---------------------------------------------------------------------------
+void *pool_alloc(size_t bytes);          // nullptr when the budget or the device is exhausted
+void pool_free(void *p);
+size_t pool_in_use();                    // bytes handed out and not yet returned
+size_t pool_budget();                    // 0 = unlimited
+void pool_set_budget(size_t bytes);
+void pool_trim();                        // return cached blocks to the device
+
+// ---------------------------------------------------------------------------
+// chain integration (chain.hip)
+// ---------------------------------------------------------------------------
+enum : int { LOAD_USER = 1, LOAD_STATE = 2 };
+enum : int { STORE_USER = 1, STORE_STATE = 2 };
+
+// Coefficients of a chain batch in scaled time tau = t / h:
+//   (B x)_i = cl_i (x_i - x_{i-1}) - cr_i (x_{i+1} - x_i),
+//   cl_i = h^2 k_i / m_i,  cr_i = h^2 k_{i+1} / m_i  (cr_{s-1} = 0).
+// For FP32 each coefficient is stored as a high part and a low part
+// (hi = fl32(c), lo = fl32(c - hi)); FP64 keeps hi only.
+template <typename T>
+struct ChainCoef {
+    const T *clh, *crh, *cll, *crl;   // [batch][s]
+    const double *h;                  // [batch] step
+};
+
+// One launch of the chain kernel over a contiguous range of instances.
+// Internal state layout (LOAD_STATE / STORE_STATE): four planes
+// [4][batch][s]: x_hi, x_lo, w_hi, w_lo with w = h * v (RK4) or the
+// half-step value w_{n+1/2} (Verlet).
+template <typename T>
+struct ChainLaunch {
+    int64_t batch;
+    int32_t s;
+    ChainCoef<T> c;
+    const T *x0, *v0;          // LOAD_USER
+    T *state;                  // LOAD_STATE / STORE_STATE
+    int64_t nsteps;            // steps advanced by this launch
+    int64_t n0;                // global step number at entry
+    int64_t out_stride;        // 0: no frames
+    T *xf, *vf;                // frames [nframes][batch][s]
+    T *xe, *ve;                // STORE_USER
+    int *nonfinite;            // set to 1 if a state is not finite at exit
+    int load_mode;
+    int store_mode;
+};
+
+struct ChainConfig {
+    int lpi;   // lanes per instance (1..64, power of two)
+    int dpl;   // degrees of freedom per lane
+};
+
+// Choose a lane-group layout for s degrees of freedom.
+ChainConfig chain_pick_config(int s);
+// Launch one integration pass.  method: OSC_RK4 / OSC_VERLET.
+template <typename T>
+osc_status chain_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, hipStream_t st);
+// Every configuration the chain kernel is built for (for tests and tuning).
+int chain_num_configs();
+ChainConfig chain_config_at(int i);
+
+// Plain baseline: one instance, one step per launch, state in device memory.
+template <typename T>
+osc_status chain_plain(const ChainLaunch<T> &a, int method, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// coefficient preparation, stability bound and energy (prep.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+osc_status chain_prepare(int64_t batch, int s, const double *m, const double *k,
+                         const double *dt, T *clh, T *crh, T *cll, T *crl, double *h,
+                         double *theta_bound, int *bad_param, hipStream_t st);
+template <typename T>
+osc_status chain_energy(int64_t batch, int s, const double *m, const double *k,
+                        const double *h, const T *x, const T *v, double *E, bool shadow,
+                        hipStream_t st);
+template <typename T>
+osc_status nonfinite_check(int64_t n, const T *x, int *flag, hipStream_t st);
+
+}  // namespace osc
+
+// Opaque handle (definition shared by the host runtime files).
+struct osc_sys {
+    osc_kind kind;
+    osc_method method;
+    osc_prec prec;
+    int32_t s;
+    int64_t batch;
+    int32_t shared;
+    hipStream_t stream;
+    int device;
+    // FP64 parameters kept on the device (energy needs M and K)
+    double *m = nullptr, *k = nullptr;   // chain: [batch][s]
+    double *h = nullptr;                 // [batch]
+    void *coef = nullptr;                // chain coefficients (4 planes of T)
+    int *flag = nullptr;                 // device non-finite flag
+    void *plain_state = nullptr;         // state planes of the plain baseline
+    double theta_max = 0.0;              // largest dt * omega bound over the batch
+    osc::ChainConfig cfg{1, 1};
+};

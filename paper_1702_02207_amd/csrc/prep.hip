@@ -1,0 +1,150 @@
+// Chain coefficient preparation, stability bound and FP64 energy kernels.
+//
+// For the fixed-free chain of eq. (2) generalised to s bodies, A = M^-1 K is
+// tridiagonal with rows (A x)_i = (k_i (x_i - x_{i-1}) - k_{i+1} (x_{i+1} - x_i)) / m_i.
+// In scaled time the integrators need B = h^2 A, i.e. per body
+//   cl_i = h^2 k_i / m_i,   cr_i = h^2 k_{i+1} / m_i   (cr_{s-1} = 0),
+// formed here in FP64 and, for FP32 state, split into hi + lo parts.
+
+#include <type_traits>
+
+#include "osc_internal.h"
+
+namespace osc {
+namespace {
+
+__device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
+    // non-negative doubles order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long *>(addr), __double_as_longlong(v));
+}
+
+template <typename T>
+__global__ void chain_prepare_kernel(int64_t batch, int s, const double *__restrict__ m,
+                                     const double *__restrict__ k, const double *dt,
+                                     T *clh, T *crh, T *cll, T *crl, double *hout,
+                                     double *theta_bound, int *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= batch * (int64_t)s) return;
+    const int64_t b = i / s;
+    const int d = (int)(i % s);
+    const double h = dt[b];
+    const double mi = m[i];
+    const double kl = k[i];
+    const double kr = (d + 1 < s) ? k[i + 1] : 0.0;
+    const bool ok = (h > 0.0) && __builtin_isfinite(h) && (mi > 0.0) && __builtin_isfinite(mi) &&
+                    (kl >= 0.0) && __builtin_isfinite(kl) && (kr >= 0.0) && __builtin_isfinite(kr);
+    if (!ok) {
+        atomicOr(bad, 1);
+        return;
+    }
+    const double cl = h * h * kl / mi;
+    const double cr = h * h * kr / mi;
+    if (d == 0 && hout) hout[b] = h;
+    clh[i] = (T)cl;
+    crh[i] = (T)cr;
+    if constexpr (std::is_same<T, float>::value) {
+        cll[i] = (T)(cl - (double)clh[i]);
+        crl[i] = (T)(cr - (double)crh[i]);
+    }
+    // Gershgorin: every eigenvalue of B lies below the largest row sum
+    // |B_ii| + sum_j |B_ij| = 2 (cl_i + cr_i); theta = sqrt(lambda_max(B)) = h omega_max.
+    atomic_max_pos(theta_bound, sqrt(2.0 * (cl + cr)));
+}
+
+// One group of G lanes (power of two <= 64) per instance; FP64 sums reduced
+// across the group with xor shuffles.
+template <typename T, int G>
+__global__ void __launch_bounds__(256) chain_energy_kernel(int64_t batch, int s, const double *__restrict__ m,
+                                                           const double *__restrict__ k,
+                                                           const double *__restrict__ hh,
+                                                           const T *__restrict__ x, const T *__restrict__ v,
+                                                           double *E, bool shadow) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = g / G;
+    const int l = (int)(g % G);
+    const bool active = b < batch;
+    double kin = 0.0, pot = 0.0, corr = 0.0;
+    if (active) {
+        const size_t base = (size_t)b * s;
+        for (int d = l; d < s; d += G) {
+            const double xd = (double)x[base + d];
+            const double xm = d > 0 ? (double)x[base + d - 1] : 0.0;
+            const double vd = (double)v[base + d];
+            const double e = xd - xm;
+            kin += m[base + d] * vd * vd;
+            pot += k[base + d] * e * e;
+            if (shadow) {
+                // (K x)_d = k_d e_d - k_{d+1} e_{d+1}
+                double f = k[base + d] * e;
+                if (d + 1 < s) f -= k[base + d + 1] * ((double)x[base + d + 1] - xd);
+                corr += f * f / m[base + d];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        kin += __shfl_xor(kin, off, G);
+        pot += __shfl_xor(pot, off, G);
+        corr += __shfl_xor(corr, off, G);
+    }
+    if (active && l == 0) {
+        if (shadow) {
+            const double h = hh[b];
+            E[b] = kin + pot - 0.25 * h * h * corr;
+        } else {
+            E[b] = 0.5 * kin + 0.5 * pot;
+        }
+    }
+}
+
+template <typename T, int G>
+void launch_energy(int64_t batch, int s, const double *m, const double *k, const double *h, const T *x,
+                   const T *v, double *E, bool shadow, hipStream_t st) {
+    const int64_t threads = batch * G;
+    const int64_t blocks = (threads + 255) / 256;
+    hipLaunchKernelGGL((chain_energy_kernel<T, G>), dim3((unsigned)blocks), dim3(256), 0, st, batch, s, m, k,
+                       h, x, v, E, shadow);
+}
+
+}  // namespace
+
+template <typename T>
+osc_status chain_prepare(int64_t batch, int s, const double *m, const double *k, const double *dt, T *clh,
+                         T *crh, T *cll, T *crl, double *h, double *theta_bound, int *bad_param,
+                         hipStream_t st) {
+    const int64_t n = batch * (int64_t)s;
+    const int64_t blocks = (n + 255) / 256;
+    if (n == 0) return OSC_OK;
+    if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "batch * s too large");
+    hipLaunchKernelGGL((chain_prepare_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, batch, s, m, k, dt,
+                       clh, crh, cll, crl, h, theta_bound, bad_param);
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+template <typename T>
+osc_status chain_energy(int64_t batch, int s, const double *m, const double *k, const double *h, const T *x,
+                        const T *v, double *E, bool shadow, hipStream_t st) {
+    if (batch == 0) return OSC_OK;
+    if (s <= 1) launch_energy<T, 1>(batch, s, m, k, h, x, v, E, shadow, st);
+    else if (s <= 2) launch_energy<T, 2>(batch, s, m, k, h, x, v, E, shadow, st);
+    else if (s <= 4) launch_energy<T, 4>(batch, s, m, k, h, x, v, E, shadow, st);
+    else if (s <= 8) launch_energy<T, 8>(batch, s, m, k, h, x, v, E, shadow, st);
+    else if (s <= 16) launch_energy<T, 16>(batch, s, m, k, h, x, v, E, shadow, st);
+    else if (s <= 32) launch_energy<T, 32>(batch, s, m, k, h, x, v, E, shadow, st);
+    else launch_energy<T, 64>(batch, s, m, k, h, x, v, E, shadow, st);
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+template osc_status chain_prepare<float>(int64_t, int, const double *, const double *, const double *, float *,
+                                         float *, float *, float *, double *, double *, int *, hipStream_t);
+template osc_status chain_prepare<double>(int64_t, int, const double *, const double *, const double *,
+                                          double *, double *, double *, double *, double *, double *, int *,
+                                          hipStream_t);
+template osc_status chain_energy<float>(int64_t, int, const double *, const double *, const double *,
+                                        const float *, const float *, double *, bool, hipStream_t);
+template osc_status chain_energy<double>(int64_t, int, const double *, const double *, const double *,
+                                         const double *, const double *, double *, bool, hipStream_t);
+
+}  // namespace osc

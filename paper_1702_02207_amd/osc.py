@@ -1,0 +1,206 @@
+"""Thin ctypes binding of libosc (include/osc.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+library.  torch supplies device memory and the current stream.  If the built
+library is missing the import of this module still works, but every call
+raises ``OscError`` -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libosc.so")
+
+OSC_OK, OSC_EINVAL, OSC_ENOTSPD, OSC_EUNSTABLE, OSC_ENOMEM, OSC_EDEVICE, OSC_ENONFINITE, \
+    OSC_ENOTSUP, OSC_ETIMEOUT, OSC_EBUSY = range(10)
+STATUS_NAMES = {0: "OSC_OK", 1: "OSC_EINVAL", 2: "OSC_ENOTSPD", 3: "OSC_EUNSTABLE", 4: "OSC_ENOMEM",
+                5: "OSC_EDEVICE", 6: "OSC_ENONFINITE", 7: "OSC_ENOTSUP", 8: "OSC_ETIMEOUT",
+                9: "OSC_EBUSY"}
+KINDS = {"chain": 0, "dense": 1}
+METHODS = {"rk4": 0, "verlet": 1}
+PRECS = {"f64": 0, "f32": 1}
+MEM_HOST, MEM_DEVICE = 0, 1
+
+
+class OscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
+                ("s", ctypes.c_int32), ("batch", ctypes.c_int64), ("shared", ctypes.c_int32),
+                ("param_mem", ctypes.c_int), ("M", ctypes.c_void_p), ("K", ctypes.c_void_p),
+                ("dt", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libosc.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OscError(OSC_EDEVICE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    sig = {
+        "osc_create": (i32, [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
+        "osc_integrate": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp]),
+        "osc_integrate_plain": (i32, [vp, vp, vp, i64, vp, vp]),
+        "osc_energy": (i32, [vp, vp, vp, vp]),
+        "osc_shadow_energy": (i32, [vp, vp, vp, vp]),
+        "osc_sync": (i32, [vp]),
+        "osc_destroy": (None, [vp]),
+        "osc_last_error": (ctypes.c_char_p, []),
+        "osc_abi_version": (i32, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != OSC_OK:
+        msg = load().osc_last_error().decode(errors="replace")
+        raise OscError(st, msg)
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class System:
+    """A batch of oscillator systems on the current GPU (one osc_sys handle).
+
+    Parameters M, K, dt are float64 numpy arrays (host) or float64 torch CUDA
+    tensors (device), laid out as include/osc.h describes.
+    """
+
+    def __init__(self, kind: str, method: str, prec: str, M, K, dt, shared: bool = True,
+                 stream=None):
+        import torch
+        lib = load()
+        self.kind, self.method, self.prec = kind, method, prec
+        self.dtype = torch.float64 if prec == "f64" else torch.float32
+        on_device = isinstance(M, torch.Tensor)
+        if on_device:
+            self._keep = [t.contiguous().to(torch.float64) for t in (M, K, dt)]
+            ptrs = [t.data_ptr() for t in self._keep]
+            M_shape = tuple(M.shape)
+        else:
+            self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (M, K, np.atleast_1d(dt))]
+            ptrs = [a.ctypes.data for a in self._keep]
+            M_shape = self._keep[0].shape
+        if kind == "chain":
+            batch, s = M_shape
+        elif shared:
+            s = M_shape[0]
+            batch = None
+        else:
+            batch, s = M_shape[0], M_shape[1]
+        self.s = int(s)
+        self._shared = shared
+        self._batch_hint = batch
+        self.stream = stream
+        self._desc = Desc(KINDS[kind], METHODS[method], PRECS[prec], self.s,
+                          int(batch if batch is not None else 0), 1 if shared else 0,
+                          MEM_DEVICE if on_device else MEM_HOST, ptrs[0], ptrs[1], ptrs[2])
+        self.handle = None
+
+    def create(self, batch: Optional[int] = None):
+        if batch is not None:
+            self._desc.batch = int(batch)
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.osc_create(ctypes.byref(self._desc), _stream_handle(self.stream), ctypes.byref(h)))
+        self.handle = h
+        self.batch = int(self._desc.batch)
+        self._keep = None
+        return self
+
+    # -- helpers -----------------------------------------------------------
+    def _state(self, t):
+        import torch
+        assert isinstance(t, torch.Tensor) and t.is_cuda, "state must be a CUDA tensor"
+        assert t.dtype == self.dtype and t.is_contiguous(), "state dtype/layout mismatch"
+        assert tuple(t.shape) == (self.batch, self.s), f"state shape {tuple(t.shape)} != {(self.batch, self.s)}"
+        return t
+
+    def integrate(self, x0, v0, nsteps: int, out_stride: int = 0, frames: bool = True,
+                  out=None):
+        """Returns (x_frames, v_frames, x_end, v_end) as new device tensors
+        (frames None when out_stride == 0 or frames is False)."""
+        import torch
+        x0, v0 = self._state(x0), self._state(v0)
+        nf = nsteps // out_stride + 1 if (out_stride > 0 and frames) else 0
+        dev = x0.device
+        if out is None:
+            xf = torch.empty((nf, self.batch, self.s), dtype=self.dtype, device=dev) if nf else None
+            vf = torch.empty((nf, self.batch, self.s), dtype=self.dtype, device=dev) if nf else None
+            xe = torch.empty_like(x0)
+            ve = torch.empty_like(v0)
+        else:
+            xf, vf, xe, ve = out
+        _check(load().osc_integrate(self.handle, _dptr(x0), _dptr(v0), int(nsteps),
+                                    int(out_stride) if nf else 0, _dptr(xf), _dptr(vf),
+                                    _dptr(xe), _dptr(ve)))
+        return xf, vf, xe, ve
+
+    def integrate_plain(self, x0, v0, nsteps: int):
+        import torch
+        x0, v0 = self._state(x0), self._state(v0)
+        xe, ve = torch.empty_like(x0), torch.empty_like(v0)
+        _check(load().osc_integrate_plain(self.handle, _dptr(x0), _dptr(v0), int(nsteps),
+                                          _dptr(xe), _dptr(ve)))
+        return xe, ve
+
+    def energy(self, x, v, shadow: bool = False):
+        import torch
+        x, v = self._state(x), self._state(v)
+        E = torch.empty(self.batch, dtype=torch.float64, device=x.device)
+        f = load().osc_shadow_energy if shadow else load().osc_energy
+        _check(f(self.handle, _dptr(x), _dptr(v), _dptr(E)))
+        return E
+
+    def sync(self):
+        _check(load().osc_sync(self.handle))
+
+    def close(self):
+        if self.handle is not None:
+            load().osc_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chain_system(method: str, prec: str, m, k, dt, stream=None) -> System:
+    return System("chain", method, prec, m, k, dt, stream=stream).create()
