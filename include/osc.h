@@ -146,6 +146,14 @@ osc_status osc_energy(osc_sys *sys, const void *x, const void *v, double *E);
  */
 osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double *Q);
 
+/*
+ * osc_dense_operator -- copy A = M^-1 K of a dense handle, formed on the GPU
+ * in FP64 by Cholesky (eq. (1)), to the device array A ([nsys][s][s]
+ * row-major, nsys = 1 when shared, else batch).  Asynchronous.  OSC_EINVAL
+ * for a chain handle.
+ */
+osc_status osc_dense_operator(osc_sys *sys, double *A);
+
 /* osc_sync -- wait for the handle's stream; returns OSC_ENONFINITE if any
  * integration since the last osc_sync produced a non-finite state. */
 osc_status osc_sync(osc_sys *sys);

@@ -4,6 +4,7 @@
 #include <new>
 #include <string>
 #include <type_traits>
+#include <vector>
 
 #include "osc_internal.h"
 
@@ -43,6 +44,9 @@ void release(osc_sys *s) {
     pool_free(s->coef);
     pool_free(s->flag);
     pool_free(s->plain_state);
+    pool_free(s->A);
+    pool_free(s->Bh);
+    pool_free(s->Bl);
     delete s;
 }
 
@@ -151,6 +155,105 @@ osc_status plain_chain(osc_sys *s, const void *x0, const void *v0, int64_t nstep
     return chain_plain<T>(a, s->method, s->stream);
 }
 
+template <typename T>
+osc_status create_dense(osc_sys *s, const osc_desc *d) {
+    const hipStream_t st = s->stream;
+    const int n = s->s;
+    const int64_t nsys = s->shared ? 1 : s->batch;
+    s->nsys = nsys;
+    const size_t ss = (size_t)n * n;
+    const size_t mbytes = nsys * ss * sizeof(double);
+    s->m = static_cast<double *>(pool_alloc(mbytes));
+    s->k = static_cast<double *>(pool_alloc(mbytes));
+    s->A = static_cast<double *>(pool_alloc(mbytes));
+    s->h = static_cast<double *>(pool_alloc(nsys * sizeof(double)));
+    s->Bh = pool_alloc(nsys * ss * sizeof(T));
+    s->Bl = std::is_same<T, float>::value ? pool_alloc(nsys * ss * sizeof(T)) : nullptr;
+    s->flag = static_cast<int *>(pool_alloc(64));
+    DevBuf Lc, Y, scratch, theta;
+    Lc.p = pool_alloc(mbytes);
+    Y.p = pool_alloc(mbytes);
+    scratch.p = pool_alloc(64);
+    theta.p = pool_alloc(nsys * sizeof(double));
+    if (!s->m || !s->k || !s->A || !s->h || !s->Bh || (std::is_same<T, float>::value && !s->Bl) || !s->flag ||
+        !Lc.p || !Y.p || !scratch.p || !theta.p)
+        return fail(OSC_ENOMEM, "device memory / HBM budget exhausted in osc_create");
+    osc_status r;
+    if ((r = copy_in(s->m, d->M, mbytes, d->param_mem, st))) return r;
+    if ((r = copy_in(s->k, d->K, mbytes, d->param_mem, st))) return r;
+    if ((r = copy_in(s->h, d->dt, nsys * sizeof(double), d->param_mem, st))) return r;
+    OSC_HIP(hipMemsetAsync(s->flag, 0, 64, st));
+    OSC_HIP(hipMemsetAsync(scratch.p, 0, 64, st));
+    OSC_HIP(hipMemsetAsync(theta.p, 0, nsys * sizeof(double), st));
+    int *notspd = static_cast<int *>(scratch.p);
+    int *bad = notspd + 1;
+    if ((r = dense_form_a(n, nsys, s->m, s->k, static_cast<double *>(Lc.p), static_cast<double *>(Y.p), s->A,
+                          notspd, st)))
+        return r;
+    if ((r = dense_prepare<T>(n, nsys, s->A, s->h, static_cast<T *>(s->Bh), static_cast<T *>(s->Bl),
+                              static_cast<double *>(theta.p), bad, st)))
+        return r;
+    int flags[2] = {0, 0};
+    OSC_HIP(hipMemcpyAsync(flags, scratch.p, sizeof(flags), hipMemcpyDeviceToHost, st));
+    std::vector<double> th(nsys);
+    OSC_HIP(hipMemcpyAsync(th.data(), theta.p, nsys * sizeof(double), hipMemcpyDeviceToHost, st));
+    OSC_HIP(hipStreamSynchronize(st));
+    if (flags[0]) return fail(OSC_ENOTSPD, "Cholesky factorisation of M failed (M is not positive definite)");
+    if (flags[1]) return fail(OSC_EINVAL, "dense parameters need finite M, K and finite dt > 0");
+    const double lim = s->method == OSC_RK4 ? kRk4Limit : kVerletLimit;
+    std::vector<double> hh(nsys);
+    bool need_power = false;
+    for (int64_t i = 0; i < nsys; ++i) need_power = need_power || !(th[i] <= lim);
+    if (need_power) OSC_HIP(hipMemcpy(hh.data(), s->h, nsys * sizeof(double), hipMemcpyDeviceToHost));
+    double worst = 0.0;
+    for (int64_t i = 0; i < nsys; ++i) {
+        double t = th[i];
+        if (!(t <= lim)) {
+            // the row-sum bound is loose: refine with power iteration, 2 % margin on omega
+            if ((r = dense_power_theta(n, s->A + i * ss, hh[i], static_cast<double *>(theta.p) + i, st))) return r;
+            OSC_HIP(hipMemcpyAsync(&t, static_cast<double *>(theta.p) + i, sizeof(double), hipMemcpyDeviceToHost,
+                                   st));
+            OSC_HIP(hipStreamSynchronize(st));
+            t *= 1.02;
+        }
+        worst = t > worst ? t : worst;
+        if (!(t <= lim))
+            return fail(OSC_EUNSTABLE, "dt * omega estimate " + std::to_string(t) + " exceeds " + std::to_string(lim));
+    }
+    s->theta_max = worst;
+    return OSC_OK;
+}
+
+template <typename T>
+DenseLaunch<T> dense_args(osc_sys *s) {
+    DenseLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.shared = s->shared ? 1 : 0;
+    a.Bh = static_cast<const T *>(s->Bh);
+    a.Bl = static_cast<const T *>(s->Bl);
+    a.h = s->h;
+    a.nonfinite = s->flag;
+    return a;
+}
+
+template <typename T>
+osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                           void *xf, void *vf, void *xe, void *ve) {
+    DenseLaunch<T> a = dense_args<T>(s);
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.nsteps = nsteps;
+    a.out_stride = out_stride;
+    a.xf = static_cast<T *>(xf);
+    a.vf = static_cast<T *>(vf);
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.load_mode = LOAD_USER;
+    a.store_mode = STORE_USER;
+    return dense_launch_vec<T>(a, s->method, s->stream);
+}
+
 }  // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
@@ -184,8 +287,9 @@ osc_status osc_create(const osc_desc *d, void *stream, osc_sys **out) {
     if (d->batch < 0) return fail(OSC_EINVAL, "batch must be >= 0");
     if (!d->M || !d->K || !d->dt) return fail(OSC_EINVAL, "M, K and dt must be non-NULL");
     if ((double)d->batch * d->s > 4.0e9) return fail(OSC_EINVAL, "batch * s too large");
-    if (d->kind == OSC_DENSE) return fail(OSC_ENOTSUP, "dense systems are not available in this build");
-    if (d->kind == OSC_CHAIN && d->s > 2048) return fail(OSC_ENOTSUP, "chains support s <= 2048");
+    if (d->s > 2048) return fail(OSC_ENOTSUP, "this build supports s <= 2048");
+    if (d->kind == OSC_DENSE && !d->shared && d->batch > 0 && (double)d->batch * d->s * d->s > 2.0e9)
+        return fail(OSC_EINVAL, "batch * s * s too large for per-instance dense systems");
 
     osc_sys *s = new (std::nothrow) osc_sys();
     if (!s) return fail(OSC_ENOMEM, "host allocation failed");
@@ -194,13 +298,15 @@ osc_status osc_create(const osc_desc *d, void *stream, osc_sys **out) {
     s->prec = d->prec;
     s->s = d->s;
     s->batch = d->batch;
-    s->shared = d->shared;
+    s->shared = d->kind == OSC_DENSE ? (d->shared ? 1 : 0) : 0;
     s->stream = static_cast<hipStream_t>(stream);
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return fail(OSC_EDEVICE, "no HIP device");
     }
-    osc_status r = d->prec == OSC_F32 ? create_chain<float>(s, d) : create_chain<double>(s, d);
+    osc_status r;
+    if (d->kind == OSC_CHAIN) r = d->prec == OSC_F32 ? create_chain<float>(s, d) : create_chain<double>(s, d);
+    else r = d->prec == OSC_F32 ? create_dense<float>(s, d) : create_dense<double>(s, d);
     if (r != OSC_OK) {
         (void)hipStreamSynchronize(s->stream);
         release(s);
@@ -219,6 +325,9 @@ osc_status osc_integrate(osc_sys *s, const void *x0, const void *v0, int64_t nst
     if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
     if (out_stride < 0) return fail(OSC_EINVAL, "out_stride must be >= 0");
     if (out_stride == 0 && (xf || vf)) return fail(OSC_EINVAL, "frames requested with out_stride == 0");
+    if (s->kind == OSC_DENSE)
+        return s->prec == OSC_F32 ? integrate_dense<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
+                                  : integrate_dense<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
     return s->prec == OSC_F32 ? integrate_chain<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                               : integrate_chain<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
 }
@@ -229,6 +338,7 @@ osc_status osc_integrate_plain(osc_sys *s, const void *x0, const void *v0, int64
     if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
     if (s->batch == 0) return OSC_OK;
     if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
+    if (s->kind == OSC_DENSE) return fail(OSC_ENOTSUP, "the plain integrator covers chains only");
     return s->prec == OSC_F32 ? plain_chain<float>(s, x0, v0, nsteps, xe, ve)
                               : plain_chain<double>(s, x0, v0, nsteps, xe, ve);
 }
@@ -238,6 +348,15 @@ static osc_status energy_common(osc_sys *s, const void *x, const void *v, double
     if (!s) return fail(OSC_EINVAL, "handle is NULL");
     if (s->batch == 0) return OSC_OK;
     if (!x || !v || !E) return fail(OSC_EINVAL, "x, v and E must be non-NULL");
+    if (s->kind == OSC_DENSE) {
+        if (s->prec == OSC_F32)
+            return dense_energy<float>(s->batch, s->s, s->shared, s->m, s->k, s->A, s->h,
+                                       static_cast<const float *>(x), static_cast<const float *>(v), E, shadow,
+                                       s->stream);
+        return dense_energy<double>(s->batch, s->s, s->shared, s->m, s->k, s->A, s->h,
+                                    static_cast<const double *>(x), static_cast<const double *>(v), E, shadow,
+                                    s->stream);
+    }
     if (s->prec == OSC_F32)
         return chain_energy<float>(s->batch, s->s, s->m, s->k, s->h, static_cast<const float *>(x),
                                    static_cast<const float *>(v), E, shadow, s->stream);
@@ -251,6 +370,15 @@ osc_status osc_energy(osc_sys *s, const void *x, const void *v, double *E) {
 
 osc_status osc_shadow_energy(osc_sys *s, const void *x, const void *v, double *Q) {
     return energy_common(s, x, v, Q, true);
+}
+
+osc_status osc_dense_operator(osc_sys *s, double *A) {
+    g_last_error.clear();
+    if (!s || !A) return fail(OSC_EINVAL, "handle and A must be non-NULL");
+    if (s->kind != OSC_DENSE) return fail(OSC_EINVAL, "not a dense handle");
+    OSC_HIP(hipMemcpyAsync(A, s->A, (size_t)s->nsys * s->s * s->s * sizeof(double), hipMemcpyDeviceToDevice,
+                           s->stream));
+    return OSC_OK;
 }
 
 osc_status osc_sync(osc_sys *s) {

@@ -100,8 +100,44 @@ template <typename T>
 osc_status chain_energy(int64_t batch, int s, const double *m, const double *k,
                         const double *h, const T *x, const T *v, double *E, bool shadow,
                         hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// dense systems (dense.hip)
+// ---------------------------------------------------------------------------
+// One integration pass over dense instances.  B = h^2 A column-major
+// (Bc[j*s + i] = B_ij), [nsys][s][s] with nsys = 1 when shared; FP32 splits
+// B into Bh + Bl.  State layout as for chains.
 template <typename T>
-osc_status nonfinite_check(int64_t n, const T *x, int *flag, hipStream_t st);
+struct DenseLaunch {
+    int64_t batch;
+    int32_t s;
+    int32_t shared;
+    const T *Bh, *Bl;
+    const double *h;           // [nsys]
+    const T *x0, *v0;
+    T *state;
+    int64_t nsteps, n0, out_stride;
+    T *xf, *vf, *xe, *ve;
+    int *nonfinite;
+    int load_mode, store_mode;
+};
+
+// A = M^-1 K for nsys systems ([nsys][s][s] row-major M, K); Lc, Y scratch of
+// the same size; status |= 1 when a Cholesky pivot is not positive.
+osc_status dense_form_a(int s, int64_t nsys, const double *M, const double *K, double *Lc, double *Y, double *A,
+                        int *status, hipStream_t st);
+// B = h^2 A (column-major, split for FP32) and per-system row-sum bounds
+// theta[sys] >= h omega_max.
+template <typename T>
+osc_status dense_prepare(int s, int64_t nsys, const double *A, const double *dt, T *Bh, T *Bl, double *theta,
+                         int *bad, hipStream_t st);
+// Power-iteration estimate h sqrt(lambda_max(A)) of one system.
+osc_status dense_power_theta(int s, const double *A, double h, double *theta, hipStream_t st);
+template <typename T>
+osc_status dense_energy(int64_t batch, int s, int shared, const double *M, const double *K, const double *A,
+                        const double *dt, const T *x, const T *v, double *E, bool shadow, hipStream_t st);
+template <typename T>
+osc_status dense_launch_vec(const DenseLaunch<T> &a, int method, hipStream_t st);
 
 }  // namespace osc
 
@@ -116,9 +152,12 @@ struct osc_sys {
     hipStream_t stream;
     int device;
     // FP64 parameters kept on the device (energy needs M and K)
-    double *m = nullptr, *k = nullptr;   // chain: [batch][s]
-    double *h = nullptr;                 // [batch]
+    double *m = nullptr, *k = nullptr;   // chain: [batch][s]; dense: M, K [nsys][s][s]
+    double *h = nullptr;                 // chain: [batch]; dense: [nsys]
     void *coef = nullptr;                // chain coefficients (4 planes of T)
+    double *A = nullptr;                 // dense: A = M^-1 K [nsys][s][s] (FP64)
+    void *Bh = nullptr, *Bl = nullptr;   // dense: h^2 A column-major, hi / lo parts
+    int64_t nsys = 0;                    // dense: number of distinct systems
     int *flag = nullptr;                 // device non-finite flag
     void *plain_state = nullptr;         // state planes of the plain baseline
     double theta_max = 0.0;              // largest dt * omega bound over the batch

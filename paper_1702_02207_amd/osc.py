@@ -59,6 +59,7 @@ def load():
         "osc_energy": (i32, [vp, vp, vp, vp]),
         "osc_shadow_energy": (i32, [vp, vp, vp, vp]),
         "osc_sync": (i32, [vp]),
+        "osc_dense_operator": (i32, [vp, vp]),
         "osc_destroy": (None, [vp]),
         "osc_last_error": (ctypes.c_char_p, []),
         "osc_abi_version": (i32, []),
@@ -96,7 +97,7 @@ class System:
     """
 
     def __init__(self, kind: str, method: str, prec: str, M, K, dt, shared: bool = True,
-                 stream=None):
+                 batch: Optional[int] = None, stream=None):
         import torch
         lib = load()
         self.kind, self.method, self.prec = kind, method, prec
@@ -112,14 +113,13 @@ class System:
             M_shape = self._keep[0].shape
         if kind == "chain":
             batch, s = M_shape
+            shared = False
         elif shared:
             s = M_shape[0]
-            batch = None
         else:
             batch, s = M_shape[0], M_shape[1]
         self.s = int(s)
         self._shared = shared
-        self._batch_hint = batch
         self.stream = stream
         self._desc = Desc(KINDS[kind], METHODS[method], PRECS[prec], self.s,
                           int(batch if batch is not None else 0), 1 if shared else 0,
@@ -180,6 +180,14 @@ class System:
         f = load().osc_shadow_energy if shadow else load().osc_energy
         _check(f(self.handle, _dptr(x), _dptr(v), _dptr(E)))
         return E
+
+    def dense_operator(self):
+        """A = M^-1 K as formed on the GPU (FP64), [nsys, s, s]."""
+        import torch
+        nsys = 1 if self._shared else self.batch
+        A = torch.empty((nsys, self.s, self.s), dtype=torch.float64, device="cuda")
+        _check(load().osc_dense_operator(self.handle, _dptr(A)))
+        return A
 
     def sync(self):
         _check(load().osc_sync(self.handle))
