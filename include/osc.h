@@ -154,6 +154,25 @@ osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double 
  */
 osc_status osc_dense_operator(osc_sys *sys, double *A);
 
+/*
+ * Launch configuration of a handle.  None of these changes a result beyond
+ * the rounding differences stated here; they exist for tuning and testing.
+ *   OSC_CFG_CHAIN_LAYOUT      chains: (lanes_per_instance << 16) | dofs_per_lane,
+ *                             one of the layouts the library is built for
+ *                             (0 = automatic).  Results are bitwise identical
+ *                             across layouts.
+ *   OSC_CFG_DENSE_KERNEL      dense: 0 automatic, 1 VALU (any s), 2 MFMA
+ *                             (FP32, shared operator, s <= 256).
+ *   OSC_CFG_STEPS_PER_LAUNCH  maximum time steps per kernel launch (0 = the
+ *                             whole run).  The state between launches keeps its
+ *                             compensation terms, so chunked and unchunked runs
+ *                             agree bitwise.
+ * Returns OSC_EINVAL for an unknown key or value, OSC_ENOTSUP for a layout or
+ * kernel this handle cannot use.
+ */
+typedef enum { OSC_CFG_CHAIN_LAYOUT = 1, OSC_CFG_DENSE_KERNEL = 2, OSC_CFG_STEPS_PER_LAUNCH = 3 } osc_config;
+osc_status osc_set_config(osc_sys *sys, osc_config key, int64_t value);
+
 /* osc_sync -- wait for the handle's stream; returns OSC_ENONFINITE if any
  * integration since the last osc_sync produced a non-finite state. */
 osc_status osc_sync(osc_sys *sys);

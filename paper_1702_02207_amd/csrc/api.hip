@@ -18,37 +18,74 @@ thread_local std::string g_last_error;
 constexpr double kRk4Limit = 2.78;
 constexpr double kVerletLimit = 1.99;
 
-size_t elem_size(osc_prec p) { return p == OSC_F64 ? sizeof(double) : sizeof(float); }
-
 struct DevBuf {
     void *p = nullptr;
     ~DevBuf() { pool_free(p); }
-    void *release() {
-        void *r = p;
-        p = nullptr;
-        return r;
-    }
 };
 
 osc_status copy_in(void *dst, const void *src, size_t bytes, osc_mem where, hipStream_t st) {
-    OSC_HIP(hipMemcpyAsync(dst, src, bytes, where == OSC_MEM_HOST ? hipMemcpyHostToDevice
-                                                                  : hipMemcpyDeviceToDevice, st));
+    if (bytes == 0) return OSC_OK;
+    OSC_HIP(hipMemcpyAsync(dst, src, bytes, where == OSC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           st));
     return OSC_OK;
 }
 
 void release(osc_sys *s) {
     if (!s) return;
-    pool_free(s->m);
-    pool_free(s->k);
-    pool_free(s->h);
-    pool_free(s->coef);
-    pool_free(s->flag);
-    pool_free(s->plain_state);
-    pool_free(s->A);
-    pool_free(s->Bh);
-    pool_free(s->Bl);
+    for (void *p : {(void *)s->m, (void *)s->k, (void *)s->h, s->coef, (void *)s->flag, s->plain_state,
+                    (void *)s->A, s->Bh, s->Bl, s->F1, s->F2, s->state})
+        pool_free(p);
     delete s;
 }
+
+size_t elem(const osc_sys *s) { return s->prec == OSC_F64 ? sizeof(double) : sizeof(float); }
+
+// State planes [4][batch][s] followed by one float per instance (the MFMA
+// path's operand scale).
+osc_status ensure_state(osc_sys *s) {
+    const size_t need = 4 * (size_t)s->batch * s->s * elem(s) + (size_t)s->batch * sizeof(float);
+    if (s->state && s->state_bytes >= need) return OSC_OK;
+    pool_free(s->state);
+    s->state = pool_alloc(need);
+    s->state_bytes = s->state ? need : 0;
+    if (!s->state) return fail(OSC_ENOMEM, "device memory exhausted for the chunked-run state");
+    return OSC_OK;
+}
+
+template <typename L>
+void set_sigma(L &, osc_sys *) {}
+void set_sigma(DenseMfmaLaunch &a, osc_sys *s) {
+    a.sigma = reinterpret_cast<float *>(static_cast<char *>(s->state) + 4 * (size_t)s->batch * s->s * sizeof(float));
+}
+
+// Advance [0, nsteps) in launches of at most steps_per_launch steps, passing
+// the compensated state through device memory between launches.
+template <typename L, typename F>
+osc_status run_chunks(osc_sys *s, L base, int64_t nsteps, F &&launch) {
+    const int64_t chunk = s->steps_per_launch > 0 ? s->steps_per_launch : nsteps;
+    if (nsteps <= chunk) {
+        base.n0 = 0;
+        base.nsteps = nsteps;
+        base.load_mode = LOAD_USER;
+        base.store_mode = STORE_USER;
+        return launch(base);
+    }
+    osc_status r = ensure_state(s);
+    if (r) return r;
+    for (int64_t n0 = 0; n0 < nsteps; n0 += chunk) {
+        L a = base;
+        a.n0 = n0;
+        a.nsteps = chunk < nsteps - n0 ? chunk : nsteps - n0;
+        a.load_mode = n0 == 0 ? LOAD_USER : LOAD_STATE;
+        a.store_mode = n0 + a.nsteps == nsteps ? STORE_USER : STORE_STATE;
+        a.state = static_cast<decltype(a.state)>(s->state);
+        set_sigma(a, s);
+        if ((r = launch(a))) return r;
+    }
+    return OSC_OK;
+}
+
+// ------------------------------------------------------------------ chains
 
 template <typename T>
 ChainCoef<T> coef_of(const osc_sys *s) {
@@ -72,25 +109,22 @@ osc_status create_chain(osc_sys *s, const osc_desc *d) {
     s->h = static_cast<double *>(pool_alloc((size_t)s->batch * sizeof(double)));
     const int planes = std::is_same<T, float>::value ? 4 : 2;
     s->coef = pool_alloc(planes * n * sizeof(T));
-    // scratch: [theta bound (double)][bad flag (int)]
     s->flag = static_cast<int *>(pool_alloc(64));
-    DevBuf scratch;
+    DevBuf scratch;   // [theta bound (double)][bad flag (int)]
     scratch.p = pool_alloc(64);
     if (!s->m || !s->k || !s->h || !s->coef || !s->flag || !scratch.p)
         return fail(OSC_ENOMEM, "device memory / HBM budget exhausted in osc_create");
     osc_status r;
     if ((r = copy_in(s->m, d->M, n * sizeof(double), d->param_mem, st))) return r;
     if ((r = copy_in(s->k, d->K, n * sizeof(double), d->param_mem, st))) return r;
-    // dt goes straight to the per-instance step buffer h.
     if ((r = copy_in(s->h, d->dt, (size_t)s->batch * sizeof(double), d->param_mem, st))) return r;
     OSC_HIP(hipMemsetAsync(s->flag, 0, 64, st));
     OSC_HIP(hipMemsetAsync(scratch.p, 0, 64, st));
     double *theta = static_cast<double *>(scratch.p);
     int *bad = reinterpret_cast<int *>(static_cast<char *>(scratch.p) + 8);
     T *base = static_cast<T *>(s->coef);
-    r = chain_prepare<T>(s->batch, s->s, s->m, s->k, s->h, base, base + n,
-                         planes == 4 ? base + 2 * n : nullptr, planes == 4 ? base + 3 * n : nullptr,
-                         /*hout=*/nullptr, theta, bad, st);
+    r = chain_prepare<T>(s->batch, s->s, s->m, s->k, s->h, base, base + n, planes == 4 ? base + 2 * n : nullptr,
+                         planes == 4 ? base + 3 * n : nullptr, /*hout=*/nullptr, theta, bad, st);
     if (r) return r;
     struct {
         double theta;
@@ -103,8 +137,8 @@ osc_status create_chain(osc_sys *s, const osc_desc *d) {
     s->theta_max = host.theta;
     const double lim = s->method == OSC_RK4 ? kRk4Limit : kVerletLimit;
     if (!(host.theta <= lim))
-        return fail(OSC_EUNSTABLE, "dt * omega bound " + std::to_string(host.theta) + " exceeds " +
-                                       std::to_string(lim));
+        return fail(OSC_EUNSTABLE,
+                    "dt * omega bound " + std::to_string(host.theta) + " exceeds " + std::to_string(lim));
     s->cfg = chain_pick_config(s->s);
     return OSC_OK;
 }
@@ -118,18 +152,14 @@ osc_status integrate_chain(osc_sys *s, const void *x0, const void *v0, int64_t n
     a.c = coef_of<T>(s);
     a.x0 = static_cast<const T *>(x0);
     a.v0 = static_cast<const T *>(v0);
-    a.state = nullptr;
-    a.nsteps = nsteps;
-    a.n0 = 0;
     a.out_stride = out_stride;
     a.xf = static_cast<T *>(xf);
     a.vf = static_cast<T *>(vf);
     a.xe = static_cast<T *>(xe);
     a.ve = static_cast<T *>(ve);
     a.nonfinite = s->flag;
-    a.load_mode = LOAD_USER;
-    a.store_mode = STORE_USER;
-    return chain_launch<T>(a, s->method, s->cfg, s->stream);
+    return run_chunks(s, a, nsteps,
+                      [&](const ChainLaunch<T> &c) { return chain_launch<T>(c, s->method, s->cfg, s->stream); });
 }
 
 template <typename T>
@@ -147,13 +177,13 @@ osc_status plain_chain(osc_sys *s, const void *x0, const void *v0, int64_t nstep
     a.v0 = static_cast<const T *>(v0);
     a.state = static_cast<T *>(s->plain_state);
     a.nsteps = nsteps;
-    a.n0 = 0;
-    a.out_stride = 0;
     a.xe = static_cast<T *>(xe);
     a.ve = static_cast<T *>(ve);
     a.nonfinite = s->flag;
     return chain_plain<T>(a, s->method, s->stream);
 }
+
+// ------------------------------------------------------------------ dense
 
 template <typename T>
 osc_status create_dense(osc_sys *s, const osc_desc *d) {
@@ -195,21 +225,18 @@ osc_status create_dense(osc_sys *s, const osc_desc *d) {
         return r;
     int flags[2] = {0, 0};
     OSC_HIP(hipMemcpyAsync(flags, scratch.p, sizeof(flags), hipMemcpyDeviceToHost, st));
-    std::vector<double> th(nsys);
+    std::vector<double> th(nsys), hh(nsys);
     OSC_HIP(hipMemcpyAsync(th.data(), theta.p, nsys * sizeof(double), hipMemcpyDeviceToHost, st));
+    OSC_HIP(hipMemcpyAsync(hh.data(), s->h, nsys * sizeof(double), hipMemcpyDeviceToHost, st));
     OSC_HIP(hipStreamSynchronize(st));
     if (flags[0]) return fail(OSC_ENOTSPD, "Cholesky factorisation of M failed (M is not positive definite)");
     if (flags[1]) return fail(OSC_EINVAL, "dense parameters need finite M, K and finite dt > 0");
     const double lim = s->method == OSC_RK4 ? kRk4Limit : kVerletLimit;
-    std::vector<double> hh(nsys);
-    bool need_power = false;
-    for (int64_t i = 0; i < nsys; ++i) need_power = need_power || !(th[i] <= lim);
-    if (need_power) OSC_HIP(hipMemcpy(hh.data(), s->h, nsys * sizeof(double), hipMemcpyDeviceToHost));
     double worst = 0.0;
     for (int64_t i = 0; i < nsys; ++i) {
-        double t = th[i];
+        double t = th[i];   // sqrt of the largest row sum of |h^2 A|: an upper bound of h omega_max
         if (!(t <= lim)) {
-            // the row-sum bound is loose: refine with power iteration, 2 % margin on omega
+            // the norm bound is loose: refine with power iteration, 2 % margin on omega
             if ((r = dense_power_theta(n, s->A + i * ss, hh[i], static_cast<double *>(theta.p) + i, st))) return r;
             OSC_HIP(hipMemcpyAsync(&t, static_cast<double *>(theta.p) + i, sizeof(double), hipMemcpyDeviceToHost,
                                    st));
@@ -218,14 +245,59 @@ osc_status create_dense(osc_sys *s, const osc_desc *d) {
         }
         worst = t > worst ? t : worst;
         if (!(t <= lim))
-            return fail(OSC_EUNSTABLE, "dt * omega estimate " + std::to_string(t) + " exceeds " + std::to_string(lim));
+            return fail(OSC_EUNSTABLE,
+                        "dt * omega estimate " + std::to_string(t) + " exceeds " + std::to_string(lim));
     }
     s->theta_max = worst;
+    s->h_shared = hh[0];
+    if (std::is_same<T, float>::value && s->shared && dense_mfma_pad(n) > 0) {
+        // FP16 operator fragments of B^ = beta h^2 A with ||B^||_inf in [1/2, 1)
+        const double rowsum = th[0] * th[0];
+        int e = 0;
+        (void)std::frexp(rowsum > 0.0 ? rowsum : 1.0, &e);
+        const double beta = std::ldexp(1.0, -e);
+        s->inv_beta = (float)std::ldexp(1.0, e);
+        const size_t fe = dense_mfma_fragment_elems(n);
+        s->F1 = pool_alloc(fe * sizeof(_Float16));
+        s->F2 = pool_alloc(fe * sizeof(_Float16));
+        if (!s->F1 || !s->F2) return fail(OSC_ENOMEM, "device memory exhausted for MFMA operator fragments");
+        if ((r = dense_mfma_fragments(n, s->A, beta * hh[0] * hh[0], static_cast<_Float16 *>(s->F1),
+                                      static_cast<_Float16 *>(s->F2), st)))
+            return r;
+        OSC_HIP(hipStreamSynchronize(st));
+    }
     return OSC_OK;
 }
 
+bool use_mfma(const osc_sys *s) {
+    const bool can = s->prec == OSC_F32 && s->F1 != nullptr;
+    return s->dense_kernel == 1 ? false : can;
+}
+
 template <typename T>
-DenseLaunch<T> dense_args(osc_sys *s) {
+osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                           void *xf, void *vf, void *xe, void *ve) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (use_mfma(s)) {
+            DenseMfmaLaunch a{};
+            a.batch = s->batch;
+            a.s = s->s;
+            a.B1 = s->F1;
+            a.B2 = s->F2;
+            a.inv_beta = s->inv_beta;
+            a.h = s->h_shared;
+            a.x0 = static_cast<const float *>(x0);
+            a.v0 = static_cast<const float *>(v0);
+            a.out_stride = out_stride;
+            a.xf = static_cast<float *>(xf);
+            a.vf = static_cast<float *>(vf);
+            a.xe = static_cast<float *>(xe);
+            a.ve = static_cast<float *>(ve);
+            a.nonfinite = s->flag;
+            return run_chunks(s, a, nsteps,
+                              [&](const DenseMfmaLaunch &c) { return dense_mfma_launch(c, s->method, s->stream); });
+        }
+    }
     DenseLaunch<T> a{};
     a.batch = s->batch;
     a.s = s->s;
@@ -234,24 +306,15 @@ DenseLaunch<T> dense_args(osc_sys *s) {
     a.Bl = static_cast<const T *>(s->Bl);
     a.h = s->h;
     a.nonfinite = s->flag;
-    return a;
-}
-
-template <typename T>
-osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
-                           void *xf, void *vf, void *xe, void *ve) {
-    DenseLaunch<T> a = dense_args<T>(s);
     a.x0 = static_cast<const T *>(x0);
     a.v0 = static_cast<const T *>(v0);
-    a.nsteps = nsteps;
     a.out_stride = out_stride;
     a.xf = static_cast<T *>(xf);
     a.vf = static_cast<T *>(vf);
     a.xe = static_cast<T *>(xe);
     a.ve = static_cast<T *>(ve);
-    a.load_mode = LOAD_USER;
-    a.store_mode = STORE_USER;
-    return dense_launch_vec<T>(a, s->method, s->stream);
+    return run_chunks(s, a, nsteps,
+                      [&](const DenseLaunch<T> &c) { return dense_launch_vec<T>(c, s->method, s->stream); });
 }
 
 }  // namespace
@@ -288,7 +351,7 @@ osc_status osc_create(const osc_desc *d, void *stream, osc_sys **out) {
     if (!d->M || !d->K || !d->dt) return fail(OSC_EINVAL, "M, K and dt must be non-NULL");
     if ((double)d->batch * d->s > 4.0e9) return fail(OSC_EINVAL, "batch * s too large");
     if (d->s > 2048) return fail(OSC_ENOTSUP, "this build supports s <= 2048");
-    if (d->kind == OSC_DENSE && !d->shared && d->batch > 0 && (double)d->batch * d->s * d->s > 2.0e9)
+    if (d->kind == OSC_DENSE && !d->shared && (double)d->batch * d->s * d->s > 2.0e9)
         return fail(OSC_EINVAL, "batch * s * s too large for per-instance dense systems");
 
     osc_sys *s = new (std::nothrow) osc_sys();
@@ -316,15 +379,51 @@ osc_status osc_create(const osc_desc *d, void *stream, osc_sys **out) {
     return OSC_OK;
 }
 
-osc_status osc_integrate(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
-                         void *xf, void *vf, void *xe, void *ve) {
+osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    switch (key) {
+        case OSC_CFG_CHAIN_LAYOUT: {
+            if (s->kind != OSC_CHAIN) return fail(OSC_EINVAL, "layout applies to chains");
+            if (value == 0) {
+                s->cfg = chain_pick_config(s->s);
+                return OSC_OK;
+            }
+            const ChainConfig c{(int)(value >> 16), (int)(value & 0xffff)};
+            for (int i = 0; i < chain_num_configs(); ++i) {
+                const ChainConfig k = chain_config_at(i);
+                if (k.lpi == c.lpi && k.dpl == c.dpl) {
+                    if ((long)c.lpi * c.dpl < s->s) return fail(OSC_ENOTSUP, "layout holds fewer than s DOFs");
+                    s->cfg = c;
+                    return OSC_OK;
+                }
+            }
+            return fail(OSC_ENOTSUP, "no kernel built for this layout");
+        }
+        case OSC_CFG_DENSE_KERNEL:
+            if (s->kind != OSC_DENSE) return fail(OSC_EINVAL, "kernel choice applies to dense systems");
+            if (value < 0 || value > 2) return fail(OSC_EINVAL, "dense kernel must be 0, 1 or 2");
+            if (value == 2 && !(s->prec == OSC_F32 && s->F1))
+                return fail(OSC_ENOTSUP, "MFMA path needs FP32, a shared operator and s <= 256");
+            s->dense_kernel = (int)value;
+            return OSC_OK;
+        case OSC_CFG_STEPS_PER_LAUNCH:
+            if (value < 0) return fail(OSC_EINVAL, "steps per launch must be >= 0");
+            s->steps_per_launch = value;
+            return OSC_OK;
+    }
+    return fail(OSC_EINVAL, "unknown configuration key");
+}
+
+osc_status osc_integrate(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride, void *xf,
+                         void *vf, void *xe, void *ve) {
     g_last_error.clear();
     if (!s) return fail(OSC_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
-    if (s->batch == 0) return OSC_OK;
-    if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
     if (out_stride < 0) return fail(OSC_EINVAL, "out_stride must be >= 0");
     if (out_stride == 0 && (xf || vf)) return fail(OSC_EINVAL, "frames requested with out_stride == 0");
+    if (s->batch == 0) return OSC_OK;
+    if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
     if (s->kind == OSC_DENSE)
         return s->prec == OSC_F32 ? integrate_dense<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                                   : integrate_dense<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
@@ -364,9 +463,7 @@ static osc_status energy_common(osc_sys *s, const void *x, const void *v, double
                                 static_cast<const double *>(v), E, shadow, s->stream);
 }
 
-osc_status osc_energy(osc_sys *s, const void *x, const void *v, double *E) {
-    return energy_common(s, x, v, E, false);
-}
+osc_status osc_energy(osc_sys *s, const void *x, const void *v, double *E) { return energy_common(s, x, v, E, false); }
 
 osc_status osc_shadow_energy(osc_sys *s, const void *x, const void *v, double *Q) {
     return energy_common(s, x, v, Q, true);

@@ -1,0 +1,419 @@
+// Dense eq. (1) systems whose A = M^-1 K is shared by many instances: every
+// stage product is a true GEMM, (s x s) . (s x instances), run on the gfx950
+// matrix cores with v_mfma_f32_16x16x32_f16.
+//
+// Workgroup: NW wavefronts and 16 instances (one MFMA column tile).  Wave w
+// owns rows [16 RT w, 16 RT (w + 1)) of the operator (RT row tiles of 16) and
+// the same rows of the 16 instances' state, kept in registers in the MFMA
+// accumulator layout (lane l, element r of row tile t: row 16 t + 4 (l/16) + r,
+// instance l % 16).  The operator stays resident in registers for the whole
+// launch; the right-hand operand of each product goes through a small padded
+// LDS buffer, which also performs the transpose from the accumulator layout
+// to the operand layout.
+//
+// Precision.  The FP16 operator B^ = beta h^2 A (beta a power of two with
+// ||B^||_inf <= 1) is split into B1 = fp16(B^) and B2 = fp16((B^ - B1) 2^11);
+// an FP32 operand u becomes u1 = fp16(u) and u2 = fp16((u - u1) 2^11).  Then
+//   B^ u ~ B1 u1 + 2^-11 (B1 u2 + B2 u1)       (three MFMAs, ~2^-22 relative)
+// accumulates in FP32.  RK4 (exact linear Taylor form, as for chains) uses
+// this three-term product for B x and B w, two terms (B1 P1 + 2^-11 B1 P2)
+// for B P and one term for B Q: each later product enters the update
+// multiplied by a further power of the small step h omega.  The state of each
+// instance is scaled by a power of two sigma so that |x| < 1 in FP16 terms;
+// powers of two keep every scaling exact.
+
+#include "osc_internal.h"
+
+namespace osc {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNC = 16;   // instances per workgroup
+constexpr float kSplit = 2048.0f;
+constexpr float kUnsplit = 1.0f / 2048.0f;
+
+__device__ __forceinline__ void comp_add(float &hi, float &lo, float y) {
+    y = y + lo;
+    const float t = hi + y;
+    lo = y - (t - hi);
+    hi = t;
+}
+
+__device__ __forceinline__ f4 mfma(half8 a, half8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+template <int RT, int NW, int METHOD>
+__global__ void __launch_bounds__(64 * NW, 1) dense_mfma_kernel(DenseMfmaLaunch a) {
+    constexpr int kNW = NW;          // waves per workgroup
+    constexpr int SP = 16 * RT * NW; // padded dimension
+    constexpr int KS = SP / 32;      // k-steps of 32
+    constexpr int LD = SP + 8;       // LDS row stride (halfs) of one instance column
+    // operand buffers: x (hi, lo), w (hi, lo), B x (hi, lo), B w (hi)
+    __shared__ __attribute__((aligned(16))) _Float16 bufA[2][kNC][LD];
+    __shared__ __attribute__((aligned(16))) _Float16 bufB[2][kNC][LD];
+    __shared__ __attribute__((aligned(16))) _Float16 bufC[2][kNC][LD];
+    __shared__ __attribute__((aligned(16))) _Float16 bufD[1][kNC][LD];
+    __shared__ float smax[kNW][kNC];
+    // compensation terms (touched once per step), lane-private slots
+    __shared__ float sxl[kNW][RT][4][64];
+    __shared__ float swl[kNW][RT][4][64];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, quad = lane >> 4;
+    const int64_t b = (int64_t)blockIdx.x * kNC + col;
+    const bool active = b < a.batch;
+    const int s = a.s;
+    const int row0 = wave * 16 * RT;
+    const size_t base = (size_t)(active ? b : 0) * s;
+    const size_t plane = (size_t)a.batch * s;
+    const double h = a.h;
+    const float ib = a.inv_beta;
+
+    // resident operator fragments
+    half8 B1r[RT][KS], B2r[RT][KS];
+    const half8 *B1 = reinterpret_cast<const half8 *>(a.B1);
+    const half8 *B2 = reinterpret_cast<const half8 *>(a.B2);
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const size_t idx = ((size_t)(wave * RT + t) * KS + q) * 64 + lane;
+            B1r[t][q] = B1[idx];
+            B2r[t][q] = B2[idx];
+        }
+
+    // state, unscaled first
+    float x[RT][4], w[RT][4];
+    float(&xl)[RT][4][64] = sxl[wave];
+    float(&wl)[RT][4][64] = swl[wave];
+    double mx = 0.0;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = row0 + 16 * t + 4 * quad + r;
+            const bool v = active && row < s;
+            const size_t i = base + row;
+            if (a.load_mode == LOAD_USER) {
+                x[t][r] = v ? a.x0[i] : 0.0f;
+                xl[t][r][lane] = 0.0f;
+                const double wd = v ? h * (double)a.v0[i] : 0.0;
+                w[t][r] = (float)wd;
+                wl[t][r][lane] = (float)(wd - (double)w[t][r]);
+            } else {
+                x[t][r] = v ? a.state[i] : 0.0f;
+                xl[t][r][lane] = v ? a.state[plane + i] : 0.0f;
+                w[t][r] = v ? a.state[2 * plane + i] : 0.0f;
+                wl[t][r][lane] = v ? a.state[3 * plane + i] : 0.0f;
+            }
+            mx = fmax(mx, fmax(fabs((double)x[t][r]), fabs((double)w[t][r])));
+        }
+    // per-instance power-of-two scale sigma (max |state| sigma in [0.5, 1)),
+    // chosen from the initial state and carried with the state across
+    // launches so that chunked runs round exactly like unchunked ones
+    float m32 = (float)mx;
+    m32 = fmaxf(m32, __shfl_xor(m32, 16, 64));
+    m32 = fmaxf(m32, __shfl_xor(m32, 32, 64));
+    if (quad == 0) smax[wave][col] = m32;
+    __syncthreads();
+    float mall = 0.0f;
+#pragma unroll
+    for (int v = 0; v < kNW; ++v) mall = fmaxf(mall, smax[v][col]);
+    int e = 0;
+    (void)frexpf(mall, &e);
+    float sigma = (mall > 0.0f && __builtin_isfinite(mall)) ? ldexpf(1.0f, -e) : 1.0f;
+    if (a.load_mode == LOAD_STATE && active) sigma = a.sigma[b];
+    if ((a.store_mode & STORE_STATE) && active && wave == 0 && quad == 0) a.sigma[b] = sigma;
+    const double inv_sigma = 1.0 / (double)sigma;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            x[t][r] *= sigma;
+            xl[t][r][lane] *= sigma;
+            w[t][r] *= sigma;
+            wl[t][r][lane] *= sigma;
+        }
+
+    // operand u -> LDS (hi plane, optionally the scaled low plane)
+    auto put = [&](_Float16 (*buf)[kNC][LD], const float (&u)[RT][4], bool two) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            half4 hv, lv;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const _Float16 hh = (_Float16)u[t][r];
+                hv[r] = hh;
+                lv[r] = (_Float16)((u[t][r] - (float)hh) * kSplit);
+            }
+            const int row = row0 + 16 * t + 4 * quad;
+            *reinterpret_cast<half4 *>(&buf[0][col][row]) = hv;
+            if (two) *reinterpret_cast<half4 *>(&buf[1][col][row]) = lv;
+        }
+    };
+    auto frag = [&](_Float16 (*buf)[kNC][LD], int p, int q) -> half8 {
+        return *reinterpret_cast<const half8 *>(&buf[p][col][32 * q + 8 * quad]);
+    };
+    // three-term product: out = B^ u with u split in buf
+    auto prod3 = [&](_Float16 (*buf)[kNC][LD], float (&out)[RT][4]) {
+        f4 am[RT], ac[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            am[t] = f4{0.f, 0.f, 0.f, 0.f};
+            ac[t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const half8 uh = frag(buf, 0, q), ul = frag(buf, 1, q);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) am[t] = mfma(B1r[t][q], uh, am[t]);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) ac[t] = mfma(B1r[t][q], ul, ac[t]);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) ac[t] = mfma(B2r[t][q], uh, ac[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[t][r] = __builtin_fmaf(ac[t][r], kUnsplit, am[t][r]);
+    };
+    // two-term product B1 (u1 + 2^-11 u2)
+    auto prod2 = [&](_Float16 (*buf)[kNC][LD], float (&out)[RT][4]) {
+        f4 am[RT], ac[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            am[t] = f4{0.f, 0.f, 0.f, 0.f};
+            ac[t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const half8 uh = frag(buf, 0, q), ul = frag(buf, 1, q);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) am[t] = mfma(B1r[t][q], uh, am[t]);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) ac[t] = mfma(B1r[t][q], ul, ac[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[t][r] = __builtin_fmaf(ac[t][r], kUnsplit, am[t][r]);
+    };
+    auto prod1 = [&](_Float16 (*buf)[kNC][LD], float (&out)[RT][4]) {
+        f4 am[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) am[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const half8 uh = frag(buf, 0, q);
+#pragma unroll
+            for (int t = 0; t < RT; ++t) am[t] = mfma(B1r[t][q], uh, am[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[t][r] = am[t][r];
+    };
+
+    float P[RT][4];   // Verlet: B^ x at the current full step (scaled units)
+    if constexpr (METHOD == OSC_VERLET) {
+        __syncthreads();
+        put(bufA, x, true);
+        __syncthreads();
+        prod3(bufA, P);
+        if (a.load_mode == LOAD_USER) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) comp_add(w[t][r], wl[t][r][lane], -0.5f * ib * P[t][r]);
+        }
+    }
+    auto vel = [&](int t, int r) -> double {
+        double wv = (double)w[t][r] + (double)wl[t][r][lane];
+        if constexpr (METHOD == OSC_VERLET) wv += 0.5 * (double)ib * (double)P[t][r];
+        return wv * inv_sigma / h;
+    };
+    const bool untouched = a.load_mode == LOAD_USER;
+    auto write_frame = [&](int64_t f, bool initial) {
+        const size_t fo = (size_t)f * plane;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + 16 * t + 4 * quad + r;
+                if (!(active && row < s)) continue;
+                const size_t i = base + row;
+                if (a.xf) a.xf[fo + i] = initial ? a.x0[i] : (float)(((double)x[t][r] + (double)xl[t][r][lane]) * inv_sigma);
+                if (a.vf) a.vf[fo + i] = initial ? a.v0[i] : (float)vel(t, r);
+            }
+    };
+
+    // RK4 coefficients in scaled units (ib = 1 / beta, a power of two)
+    const float c1 = -0.5f * ib, c2 = -ib / 6.0f, c3 = ib * ib / 24.0f;
+    const float d1 = -ib, d2 = -0.5f * ib, d3 = ib * ib / 6.0f, d4 = ib * ib / 24.0f;
+
+    int64_t n = a.n0;
+    const int64_t nend = a.n0 + a.nsteps;
+    const int64_t stride = a.out_stride;
+    if (stride > 0 && untouched && n % stride == 0) write_frame(n / stride, true);
+    while (n < nend) {
+        int64_t stop = nend;
+        if (stride > 0) {
+            const int64_t nf = (n / stride + 1) * stride;
+            stop = nf < stop ? nf : stop;
+        }
+        for (int64_t it = n; it < stop; ++it) {
+            if constexpr (METHOD == OSC_RK4) {
+                // each product is folded into dx, dw and written out as the next
+                // operand as soon as it is formed, so only one is live at a time
+                float dx[RT][4], dw[RT][4], T[RT][4];
+                __syncthreads();
+                put(bufA, x, true);
+                put(bufB, w, true);
+                __syncthreads();
+                prod3(bufA, T);   // P = B^ x
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dx[t][r] = __builtin_fmaf(c1, T[t][r], w[t][r]);
+                        dw[t][r] = d1 * T[t][r];
+                    }
+                put(bufC, T, true);
+                prod3(bufB, T);   // Q = B^ w
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dx[t][r] = __builtin_fmaf(c2, T[t][r], dx[t][r]);
+                        dw[t][r] = __builtin_fmaf(d2, T[t][r], dw[t][r]);
+                    }
+                put(bufD, T, false);
+                __syncthreads();
+                prod2(bufC, T);   // P2 = B^ P
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dx[t][r] = __builtin_fmaf(c3, T[t][r], dx[t][r]);
+                        dw[t][r] = __builtin_fmaf(d3, T[t][r], dw[t][r]);
+                    }
+                prod1(bufD, T);   // Q2 = B^ Q
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dw[t][r] = __builtin_fmaf(d4, T[t][r], dw[t][r]);
+                        comp_add(x[t][r], xl[t][r][lane], dx[t][r]);
+                        comp_add(w[t][r], wl[t][r][lane], dw[t][r]);
+                    }
+            } else {
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) comp_add(x[t][r], xl[t][r][lane], w[t][r]);
+                __syncthreads();
+                put(bufA, x, true);
+                __syncthreads();
+                prod3(bufA, P);
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) comp_add(w[t][r], wl[t][r][lane], -ib * P[t][r]);
+            }
+        }
+        n = stop;
+        if (stride > 0 && n % stride == 0) write_frame(n / stride, false);
+    }
+
+    const bool copy_input = untouched && a.nsteps == 0;
+    bool ok = true;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = row0 + 16 * t + 4 * quad + r;
+            if (!(active && row < s)) continue;
+            const size_t i = base + row;
+            ok = ok && __builtin_isfinite(x[t][r]) && __builtin_isfinite(w[t][r]);
+            if (a.store_mode & STORE_STATE) {
+                a.state[i] = (float)((double)x[t][r] * inv_sigma);
+                a.state[plane + i] = (float)((double)xl[t][r][lane] * inv_sigma);
+                a.state[2 * plane + i] = (float)((double)w[t][r] * inv_sigma);
+                a.state[3 * plane + i] = (float)((double)wl[t][r][lane] * inv_sigma);
+            }
+            if (a.store_mode & STORE_USER) {
+                if (a.xe) a.xe[i] = copy_input ? a.x0[i] : (float)(((double)x[t][r] + (double)xl[t][r][lane]) * inv_sigma);
+                if (a.ve) a.ve[i] = copy_input ? a.v0[i] : (float)vel(t, r);
+            }
+        }
+    if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
+}
+
+// Operator fragments: for row tile T, k-step q, lane l, element j:
+// row = 16 T + l % 16, k = 32 q + 8 (l / 16) + j.
+__global__ void dense_mfma_fragments_kernel(int s, int sp, const double *__restrict__ A, double scale,
+                                            _Float16 *B1, _Float16 *B2) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ks = sp / 32;
+    const int64_t total = (int64_t)(sp / 16) * ks * 64 * 8;
+    if (idx >= total) return;
+    const int j = (int)(idx % 8);
+    const int l = (int)((idx / 8) % 64);
+    const int q = (int)((idx / 512) % ks);
+    const int T = (int)(idx / (512 * (int64_t)ks));
+    const int row = 16 * T + l % 16, k = 32 * q + 8 * (l / 16) + j;
+    const double v = (row < s && k < s) ? scale * A[(size_t)row * s + k] : 0.0;
+    const _Float16 h1 = (_Float16)(float)v;
+    B1[idx] = h1;
+    B2[idx] = (_Float16)(float)((v - (double)(float)h1) * 2048.0);
+}
+
+template <int RT, int NW>
+void launch_rt(const DenseMfmaLaunch &a, int method, hipStream_t st) {
+    const unsigned blocks = (unsigned)((a.batch + kNC - 1) / kNC);
+    if (method == OSC_RK4)
+        hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_RK4>), dim3(blocks), dim3(64 * NW), 0, st, a);
+    else
+        hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_VERLET>), dim3(blocks), dim3(64 * NW), 0, st, a);
+}
+
+}  // namespace
+
+int dense_mfma_pad(int s) { return s <= 256 ? ((s + 63) / 64) * 64 : 0; }
+
+size_t dense_mfma_fragment_elems(int s) {
+    const int sp = dense_mfma_pad(s);
+    return (size_t)(sp / 16) * (sp / 32) * 64 * 8;
+}
+
+osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *B1, _Float16 *B2, hipStream_t st) {
+    const int sp = dense_mfma_pad(s);
+    if (!sp) return fail(OSC_ENOTSUP, "MFMA path needs s <= 256");
+    const int64_t total = (int64_t)dense_mfma_fragment_elems(s);
+    hipLaunchKernelGGL(dense_mfma_fragments_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, s, sp,
+                       A, scale, B1, B2);
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+osc_status dense_mfma_launch(const DenseMfmaLaunch &a, int method, hipStream_t st) {
+    if (a.batch == 0) return OSC_OK;
+    if ((a.batch + kNC - 1) / kNC > 0x7fffffff) return fail(OSC_EINVAL, "batch too large for one launch");
+    // 32 rows per wave: the operator takes 128 registers per lane, which
+    // leaves room for two waves per SIMD
+    switch (dense_mfma_pad(a.s) / 64) {
+        case 1: launch_rt<2, 2>(a, method, st); break;
+        case 2: launch_rt<2, 4>(a, method, st); break;
+        case 3: launch_rt<2, 6>(a, method, st); break;
+        case 4: launch_rt<2, 8>(a, method, st); break;
+        default: return fail(OSC_ENOTSUP, "MFMA path needs s <= 256");
+    }
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+}  // namespace osc

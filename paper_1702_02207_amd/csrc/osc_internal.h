@@ -139,6 +139,26 @@ osc_status dense_energy(int64_t batch, int s, int shared, const double *M, const
 template <typename T>
 osc_status dense_launch_vec(const DenseLaunch<T> &a, int method, hipStream_t st);
 
+// Shared-operator MFMA path (dense_mfma.hip), FP32 state, s <= 256.
+struct DenseMfmaLaunch {
+    int64_t batch;
+    int32_t s;
+    const void *B1, *B2;       // FP16 operator fragments (hi, scaled lo)
+    float inv_beta;            // 1 / beta, a power of two
+    double h;
+    const float *x0, *v0;
+    float *state;
+    float *sigma;              // [batch] per-instance scale, carried with the state
+    int64_t nsteps, n0, out_stride;
+    float *xf, *vf, *xe, *ve;
+    int *nonfinite;
+    int load_mode, store_mode;
+};
+int dense_mfma_pad(int s);                       // padded size (multiple of 64), 0 if s > 256
+size_t dense_mfma_fragment_elems(int s);         // FP16 elements per operator part
+osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *B1, _Float16 *B2, hipStream_t st);
+osc_status dense_mfma_launch(const DenseMfmaLaunch &a, int method, hipStream_t st);
+
 }  // namespace osc
 
 // Opaque handle (definition shared by the host runtime files).
@@ -158,6 +178,14 @@ struct osc_sys {
     double *A = nullptr;                 // dense: A = M^-1 K [nsys][s][s] (FP64)
     void *Bh = nullptr, *Bl = nullptr;   // dense: h^2 A column-major, hi / lo parts
     int64_t nsys = 0;                    // dense: number of distinct systems
+    void *F1 = nullptr, *F2 = nullptr;   // dense shared FP32: MFMA operator fragments
+    float inv_beta = 1.0f;
+    double h_shared = 0.0;
+    // configuration (osc_set_config)
+    int dense_kernel = 0;                // 0 auto, 1 VALU, 2 MFMA
+    int64_t steps_per_launch = 0;        // 0: whole run in one launch
+    void *state = nullptr;               // internal state planes for chunked runs
+    size_t state_bytes = 0;
     int *flag = nullptr;                 // device non-finite flag
     void *plain_state = nullptr;         // state planes of the plain baseline
     double theta_max = 0.0;              // largest dt * omega bound over the batch

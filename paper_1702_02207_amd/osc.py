@@ -25,6 +25,7 @@ KINDS = {"chain": 0, "dense": 1}
 METHODS = {"rk4": 0, "verlet": 1}
 PRECS = {"f64": 0, "f32": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
+CFG_CHAIN_LAYOUT, CFG_DENSE_KERNEL, CFG_STEPS_PER_LAUNCH = 1, 2, 3
 
 
 class OscError(RuntimeError):
@@ -60,6 +61,7 @@ def load():
         "osc_shadow_energy": (i32, [vp, vp, vp, vp]),
         "osc_sync": (i32, [vp]),
         "osc_dense_operator": (i32, [vp, vp]),
+        "osc_set_config": (i32, [vp, i32, i64]),
         "osc_destroy": (None, [vp]),
         "osc_last_error": (ctypes.c_char_p, []),
         "osc_abi_version": (i32, []),
@@ -180,6 +182,12 @@ class System:
         f = load().osc_shadow_energy if shadow else load().osc_energy
         _check(f(self.handle, _dptr(x), _dptr(v), _dptr(E)))
         return E
+
+    def set_config(self, key: int, value: int):
+        """osc_set_config: CFG_CHAIN_LAYOUT ((lanes << 16) | dofs_per_lane),
+        CFG_DENSE_KERNEL (0 auto, 1 VALU, 2 MFMA), CFG_STEPS_PER_LAUNCH."""
+        _check(load().osc_set_config(self.handle, int(key), int(value)))
+        return self
 
     def dense_operator(self):
         """A = M^-1 K as formed on the GPU (FP64), [nsys, s, s]."""

@@ -104,3 +104,50 @@ def test_dense_rejects_non_spd_and_unstable():
     with pytest.raises(osc.OscError) as e:
         osc.System("dense", "verlet", "f32", M, K, [0.25], shared=True, batch=1).create()
     assert e.value.status == osc.OSC_EUNSTABLE
+
+
+def _run(sysm, w, nsteps, stride):
+    import torch
+    x0 = torch.as_tensor(w.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=torch.float32, device="cuda")
+    xf, vf, xe, ve = sysm.integrate(x0, v0, nsteps, stride)
+    sysm.sync()
+    return [t.double().cpu().numpy() for t in (xf, vf, xe, ve)]
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+@pytest.mark.parametrize("s,batch", [(3, 5), (64, 17), (100, 33), (200, 16), (256, 40)])
+def test_dense_mfma_matches_oracle(method, s, batch):
+    """Shared operator, FP32: the MFMA path (FP16 three-term products with
+    FP32 accumulation) against the FP64 oracle."""
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(300 + s, s, batch, 2000, 500, vscale=0.01)
+    sysm = osc.System("dense", method, "f32", w.M, w.K, w.dt, shared=True, batch=batch).create()
+    sysm.set_config(osc.CFG_DENSE_KERNEL, 2)
+    xf, vf, xe, ve = _run(sysm, w, w.nsteps, w.out_stride)
+    sysm.close()
+    x0, v0 = f32_inputs(w)
+    rx, rv, rxe, _ = oracle_dense(method, w, x0=x0, v0=v0)
+    ex, ev = _err(xf, rx), _err(vf, rv)
+    print(f"mfma {method} s={s}: x {ex.max():.2e} v {ev.max():.2e}")
+    assert ex.max() < TOL_F32
+    assert ev.max() < TOL_F32
+    assert _err(xe, rxe).max() < TOL_F32
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_dense_mfma_and_valu_agree_and_chunking_is_bitwise(method):
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(77, 130, 37, 900, 300, vscale=0.01)
+    sysm = osc.System("dense", method, "f32", w.M, w.K, w.dt, shared=True, batch=37).create()
+    whole = _run(sysm, w, 900, 300)
+    sysm.set_config(osc.CFG_STEPS_PER_LAUNCH, 250)
+    chunked = _run(sysm, w, 900, 300)
+    for a, b in zip(whole, chunked):
+        np.testing.assert_array_equal(a, b)
+    sysm.set_config(osc.CFG_STEPS_PER_LAUNCH, 0)
+    sysm.set_config(osc.CFG_DENSE_KERNEL, 1)
+    valu = _run(sysm, w, 900, 300)
+    sysm.close()
+    assert _err(whole[0], valu[0]).max() < 2 * TOL_F32
+    assert _err(whole[1], valu[1]).max() < 2 * TOL_F32
