@@ -161,16 +161,25 @@ osc_status osc_dense_operator(osc_sys *sys, double *A);
  *                             one of the layouts the library is built for
  *                             (0 = automatic).  Results are bitwise identical
  *                             across layouts.
- *   OSC_CFG_DENSE_KERNEL      dense: 0 automatic, 1 VALU (any s), 2 MFMA
- *                             (FP32, shared operator, s <= 256).
+ *   OSC_CFG_DENSE_KERNEL      dense: 0 automatic, 1 VALU, one workgroup per
+ *                             instance (any s), 2 MFMA (FP32, shared operator,
+ *                             s <= 256), 3 split (each step two kernels over
+ *                             many workgroups; for few instances of large s).
  *   OSC_CFG_STEPS_PER_LAUNCH  maximum time steps per kernel launch (0 = the
  *                             whole run).  The state between launches keeps its
  *                             compensation terms, so chunked and unchunked runs
  *                             agree bitwise.
+ *   OSC_CFG_GRAPH_STEPS       split dense path: steps per captured hipGraph
+ *                             that is replayed (0 = launch eagerly; default 64).
  * Returns OSC_EINVAL for an unknown key or value, OSC_ENOTSUP for a layout or
  * kernel this handle cannot use.
  */
-typedef enum { OSC_CFG_CHAIN_LAYOUT = 1, OSC_CFG_DENSE_KERNEL = 2, OSC_CFG_STEPS_PER_LAUNCH = 3 } osc_config;
+typedef enum {
+    OSC_CFG_CHAIN_LAYOUT = 1,
+    OSC_CFG_DENSE_KERNEL = 2,
+    OSC_CFG_STEPS_PER_LAUNCH = 3,
+    OSC_CFG_GRAPH_STEPS = 4
+} osc_config;
 osc_status osc_set_config(osc_sys *sys, osc_config key, int64_t value);
 
 /* osc_sync -- wait for the handle's stream; returns OSC_ENONFINITE if any

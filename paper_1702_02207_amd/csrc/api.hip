@@ -33,8 +33,9 @@ osc_status copy_in(void *dst, const void *src, size_t bytes, osc_mem where, hipS
 void release(osc_sys *s) {
     if (!s) return;
     for (void *p : {(void *)s->m, (void *)s->k, (void *)s->h, s->coef, (void *)s->flag, s->plain_state,
-                    (void *)s->A, s->Bh, s->Bl, s->F1, s->F2, s->state})
+                    (void *)s->A, s->Bh, s->Bl, s->F1, s->F2, s->state, s->split_scratch})
         pool_free(p);
+    if (s->split_graph) (void)hipGraphExecDestroy(s->split_graph);
     delete s;
 }
 
@@ -271,12 +272,67 @@ osc_status create_dense(osc_sys *s, const osc_desc *d) {
 
 bool use_mfma(const osc_sys *s) {
     const bool can = s->prec == OSC_F32 && s->F1 != nullptr;
-    return s->dense_kernel == 1 ? false : can;
+    return (s->dense_kernel == 0 || s->dense_kernel == 2) ? can : false;
+}
+
+// Split path by default for few instances of large s: one workgroup per
+// instance would leave most of the GPU idle.
+bool use_split(const osc_sys *s) {
+    if (s->dense_kernel == 3) return true;
+    if (s->dense_kernel != 0) return false;
+    return s->s > 256 && s->batch * ((s->s + 63) / 64) <= 1024;
+}
+
+template <typename T>
+osc_status integrate_split(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                           void *xf, void *vf, void *xe, void *ve) {
+    osc_status r = ensure_state(s);
+    if (r) return r;
+    const size_t n = (size_t)s->batch * s->s;
+    if (!s->split_scratch) {
+        s->split_scratch = pool_alloc(2 * n * sizeof(T) + 64);
+        if (!s->split_scratch) return fail(OSC_ENOMEM, "device memory exhausted for the split dense path");
+    }
+    DenseSplitLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.shared = s->shared ? 1 : 0;
+    a.Bh = static_cast<const T *>(s->Bh);
+    a.Bl = static_cast<const T *>(s->Bl);
+    a.h = s->h;
+    a.state = static_cast<T *>(s->state);
+    a.P = static_cast<T *>(s->split_scratch);
+    a.Q = a.P + n;
+    a.counter = reinterpret_cast<int64_t *>(a.Q + n);
+    a.out_stride = out_stride;
+    a.xf = static_cast<T *>(xf);
+    a.vf = static_cast<T *>(vf);
+    a.nonfinite = s->flag;
+    // the graph replays phase kernels only: key on what they read
+    static_assert(sizeof(DenseSplitLaunch<T>) <= sizeof(s->split_key), "graph key too small");
+    unsigned char key[sizeof(s->split_key)] = {};
+    std::memcpy(key, &a, sizeof(a));
+    if (std::memcmp(key, s->split_key, sizeof(key)) != 0 && s->split_graph) {
+        (void)hipGraphExecDestroy(s->split_graph);
+        s->split_graph = nullptr;
+    }
+    std::memcpy(s->split_key, key, sizeof(key));
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.n0 = 0;
+    a.nsteps = nsteps;
+    a.load_mode = LOAD_USER;
+    a.store_mode = STORE_USER;
+    const int64_t gsteps = s->stream ? s->graph_steps : 0;   // no capture on the null stream
+    return dense_split_run<T>(a, s->method, s->stream, &s->split_graph, &s->split_graph_len, gsteps);
 }
 
 template <typename T>
 osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
                            void *xf, void *vf, void *xe, void *ve) {
+    if (!use_mfma(s) && use_split(s)) return integrate_split<T>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
     if constexpr (std::is_same<T, float>::value) {
         if (use_mfma(s)) {
             DenseMfmaLaunch a{};
@@ -402,7 +458,7 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
         }
         case OSC_CFG_DENSE_KERNEL:
             if (s->kind != OSC_DENSE) return fail(OSC_EINVAL, "kernel choice applies to dense systems");
-            if (value < 0 || value > 2) return fail(OSC_EINVAL, "dense kernel must be 0, 1 or 2");
+            if (value < 0 || value > 3) return fail(OSC_EINVAL, "dense kernel must be 0, 1, 2 or 3");
             if (value == 2 && !(s->prec == OSC_F32 && s->F1))
                 return fail(OSC_ENOTSUP, "MFMA path needs FP32, a shared operator and s <= 256");
             s->dense_kernel = (int)value;
@@ -410,6 +466,10 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
         case OSC_CFG_STEPS_PER_LAUNCH:
             if (value < 0) return fail(OSC_EINVAL, "steps per launch must be >= 0");
             s->steps_per_launch = value;
+            return OSC_OK;
+        case OSC_CFG_GRAPH_STEPS:
+            if (value < 0 || value > 4096) return fail(OSC_EINVAL, "graph steps must be in [0, 4096]");
+            s->graph_steps = value;
             return OSC_OK;
     }
     return fail(OSC_EINVAL, "unknown configuration key");

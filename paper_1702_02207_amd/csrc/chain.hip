@@ -128,12 +128,12 @@ __device__ __forceinline__ void comp_add(T &hi, T &lo, T y) {
 template <typename T>
 __device__ __forceinline__ bool finite(T v) { return __builtin_isfinite(v); }
 
+// One lane of the group that integrates instance b of launch a (sl = lane
+// within the group).  Lanes of an instance outside the batch run on zeros so
+// that their group still answers the DPP exchanges of a full wave.
 template <typename T, int DPL, int LPI, int METHOD>
-__global__ void __launch_bounds__(256) chain_kernel(ChainLaunch<T> a) {
+__device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t b, const int sl) {
     constexpr bool COMP = std::is_same<T, float>::value;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t b = g / LPI;
-    const int sl = (int)(g % LPI);
     const bool active = b < a.batch;
     const int s = a.s;
     const int d0 = sl * DPL;
@@ -275,6 +275,23 @@ __global__ void __launch_bounds__(256) chain_kernel(ChainLaunch<T> a) {
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
 }
 
+template <typename T, int DPL, int LPI, int METHOD>
+__global__ void __launch_bounds__(256) chain_kernel(ChainLaunch<T> a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    chain_run<T, DPL, LPI, METHOD>(a, g / LPI, (int)(g % LPI));
+}
+
+// Work list: lane group i integrates items[i] (an instance of any launch
+// whose s fits the layout; step ranges may differ between items).
+template <typename T, int DPL, int LPI, int METHOD>
+__global__ void __launch_bounds__(256) chain_items_kernel(const ChainItem<T> *__restrict__ items, int64_t nitems) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = g / LPI;
+    if (i >= nitems) return;   // whole groups only: LPI divides the wave
+    const ChainLaunch<T> a = items[i].L;
+    chain_run<T, DPL, LPI, METHOD>(a, items[i].b, (int)(g % LPI));
+}
+
 // --------------------------------------------------------------------------
 // configuration table
 // --------------------------------------------------------------------------
@@ -290,25 +307,36 @@ constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 template <typename T, int METHOD>
 using KernelFn = void (*)(ChainLaunch<T>);
-
-template <typename T, int METHOD, int I>
-constexpr KernelFn<T, METHOD> kernel_at() {
-    return &chain_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD>;
-}
+template <typename T, int METHOD>
+using ItemsFn = void (*)(const ChainItem<T> *, int64_t);
 
 template <typename T, int METHOD, int... I>
 constexpr auto make_table(std::integer_sequence<int, I...>) {
     struct Table {
         KernelFn<T, METHOD> f[sizeof...(I)];
+        ItemsFn<T, METHOD> g[sizeof...(I)];
     };
-    return Table{{kernel_at<T, METHOD, I>()...}};
+    return Table{{&chain_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD>...},
+                 {&chain_items_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD>...}};
+}
+
+template <typename T, int METHOD>
+const auto &table() {
+    static const auto t = make_table<T, METHOD>(std::make_integer_sequence<int, kNumConfigs>{});
+    return t;
 }
 
 template <typename T, int METHOD>
 KernelFn<T, METHOD> lookup(ChainConfig cfg) {
-    static const auto table = make_table<T, METHOD>(std::make_integer_sequence<int, kNumConfigs>{});
     for (int i = 0; i < kNumConfigs; ++i)
-        if (kConfigs[i].lpi == cfg.lpi && kConfigs[i].dpl == cfg.dpl) return table.f[i];
+        if (kConfigs[i].lpi == cfg.lpi && kConfigs[i].dpl == cfg.dpl) return table<T, METHOD>().f[i];
+    return nullptr;
+}
+
+template <typename T, int METHOD>
+ItemsFn<T, METHOD> lookup_items(ChainConfig cfg) {
+    for (int i = 0; i < kNumConfigs; ++i)
+        if (kConfigs[i].lpi == cfg.lpi && kConfigs[i].dpl == cfg.dpl) return table<T, METHOD>().g[i];
     return nullptr;
 }
 
@@ -356,6 +384,27 @@ osc_status chain_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, hi
 
 template osc_status chain_launch<float>(const ChainLaunch<float> &, int, ChainConfig, hipStream_t);
 template osc_status chain_launch<double>(const ChainLaunch<double> &, int, ChainConfig, hipStream_t);
+
+template <typename T>
+osc_status chain_launch_items(const ChainItem<T> *items, int64_t nitems, int method, ChainConfig cfg,
+                              hipStream_t st) {
+    if (nitems == 0) return OSC_OK;
+    const int64_t blocks = (nitems * cfg.lpi + 255) / 256;
+    if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "work list too long for one launch");
+    if (method == OSC_RK4) {
+        auto f = lookup_items<T, OSC_RK4>(cfg);
+        if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, items, nitems);
+    } else {
+        auto f = lookup_items<T, OSC_VERLET>(cfg);
+        if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, items, nitems);
+    }
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+template osc_status chain_launch_items<float>(const ChainItem<float> *, int64_t, int, ChainConfig, hipStream_t);
+template osc_status chain_launch_items<double>(const ChainItem<double> *, int64_t, int, ChainConfig, hipStream_t);
 
 // --------------------------------------------------------------------------
 // plain baseline: one instance, one step per launch, state in device memory

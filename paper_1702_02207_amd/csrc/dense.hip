@@ -227,12 +227,11 @@ __global__ void __launch_bounds__(256) dense_energy_kernel(int s, int shared, co
 // One workgroup per instance; lane t owns rows t, t + THREADS, ... (RPT rows).
 // Operand vectors live in LDS; B streams from L2 (column-major, coalesced).
 template <typename T, int METHOD, int THREADS, int RPT>
-__global__ void __launch_bounds__(THREADS) dense_vec_kernel(DenseLaunch<T> a) {
+__device__ __forceinline__ void dense_vec_run(const DenseLaunch<T> &a, const int64_t b) {
     constexpr bool COMP = std::is_same<T, float>::value;
     extern __shared__ unsigned char smem_raw[];
     T *su = reinterpret_cast<T *>(smem_raw);   // operand 1 (x or P)
     T *sv = su + a.s;                          // operand 2 (w or Q)
-    const int64_t b = blockIdx.x;
     const int s = a.s;
     const size_t ss = (size_t)s * s;
     const T *Bh = a.Bh + (a.shared ? 0 : b * ss);
@@ -405,6 +404,38 @@ __global__ void __launch_bounds__(THREADS) dense_vec_kernel(DenseLaunch<T> a) {
 }
 
 template <typename T, int METHOD, int THREADS, int RPT>
+__global__ void __launch_bounds__(THREADS) dense_vec_kernel(DenseLaunch<T> a) {
+    dense_vec_run<T, METHOD, THREADS, RPT>(a, blockIdx.x);
+}
+
+template <typename T, int METHOD, int THREADS, int RPT>
+__global__ void __launch_bounds__(THREADS) dense_items_kernel(const DenseItem<T> *__restrict__ items) {
+    const DenseLaunch<T> a = items[blockIdx.x].L;
+    dense_vec_run<T, METHOD, THREADS, RPT>(a, items[blockIdx.x].b);
+}
+
+template <typename T, int METHOD, int THREADS, int RPT>
+void launch_items(const DenseItem<T> *items, int64_t n, int smax, hipStream_t st) {
+    const size_t lds = 2 * (size_t)smax * sizeof(T);
+    hipLaunchKernelGGL((dense_items_kernel<T, METHOD, THREADS, RPT>), dim3((unsigned)n), dim3(THREADS), lds, st,
+                       items);
+}
+
+template <typename T, int METHOD>
+osc_status launch_items_m(const DenseItem<T> *items, int64_t n, int smax, hipStream_t st) {
+    switch (dense_vec_bucket(smax)) {
+        case 0: launch_items<T, METHOD, 64, 1>(items, n, smax, st); break;
+        case 1: launch_items<T, METHOD, 256, 1>(items, n, smax, st); break;
+        case 2: launch_items<T, METHOD, 256, 2>(items, n, smax, st); break;
+        case 3: launch_items<T, METHOD, 256, 4>(items, n, smax, st); break;
+        case 4: launch_items<T, METHOD, 256, 8>(items, n, smax, st); break;
+        default: return fail(OSC_ENOTSUP, "dense systems support s <= 2048");
+    }
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+template <typename T, int METHOD, int THREADS, int RPT>
 void launch_vec(const DenseLaunch<T> &a, hipStream_t st) {
     const size_t lds = 2 * (size_t)a.s * sizeof(T);
     hipLaunchKernelGGL((dense_vec_kernel<T, METHOD, THREADS, RPT>), dim3((unsigned)a.batch), dim3(THREADS), lds, st,
@@ -424,6 +455,25 @@ osc_status launch_vec_m(const DenseLaunch<T> &a, hipStream_t st) {
 }
 
 }  // namespace
+
+int dense_vec_bucket(int s) {
+    if (s <= 64) return 0;
+    if (s <= 256) return 1;
+    if (s <= 512) return 2;
+    if (s <= 1024) return 3;
+    if (s <= 2048) return 4;
+    return -1;
+}
+
+template <typename T>
+osc_status dense_launch_items(const DenseItem<T> *items, int64_t nitems, int smax, int method, hipStream_t st) {
+    if (nitems == 0) return OSC_OK;
+    if (nitems > 0x7fffffff) return fail(OSC_EINVAL, "work list too long for one launch");
+    return method == OSC_RK4 ? launch_items_m<T, OSC_RK4>(items, nitems, smax, st)
+                             : launch_items_m<T, OSC_VERLET>(items, nitems, smax, st);
+}
+template osc_status dense_launch_items<float>(const DenseItem<float> *, int64_t, int, int, hipStream_t);
+template osc_status dense_launch_items<double>(const DenseItem<double> *, int64_t, int, int, hipStream_t);
 
 // ------------------------------------------------------------- host helpers
 

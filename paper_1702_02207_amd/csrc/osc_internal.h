@@ -71,6 +71,13 @@ struct ChainLaunch {
     int store_mode;
 };
 
+// One entry of a work list: instance b of launch L.
+template <typename T>
+struct ChainItem {
+    ChainLaunch<T> L;
+    int64_t b;
+};
+
 struct ChainConfig {
     int lpi;   // lanes per instance (1..64, power of two)
     int dpl;   // degrees of freedom per lane
@@ -81,6 +88,10 @@ ChainConfig chain_pick_config(int s);
 // Launch one integration pass.  method: OSC_RK4 / OSC_VERLET.
 template <typename T>
 osc_status chain_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, hipStream_t st);
+// Launch a work list (device array of items, all of whose s fit cfg).
+template <typename T>
+osc_status chain_launch_items(const ChainItem<T> *items, int64_t nitems, int method, ChainConfig cfg,
+                              hipStream_t st);
 // Every configuration the chain kernel is built for (for tests and tuning).
 int chain_num_configs();
 ChainConfig chain_config_at(int i);
@@ -122,6 +133,18 @@ struct DenseLaunch {
     int load_mode, store_mode;
 };
 
+template <typename T>
+struct DenseItem {
+    DenseLaunch<T> L;
+    int64_t b;
+};
+// Work list of dense instances, one workgroup each; every item's s must be
+// <= smax, which selects the kernel shape.
+template <typename T>
+osc_status dense_launch_items(const DenseItem<T> *items, int64_t nitems, int smax, int method, hipStream_t st);
+// kernel shape bucket of the generic dense integrator for s (0..4)
+int dense_vec_bucket(int s);
+
 // A = M^-1 K for nsys systems ([nsys][s][s] row-major M, K); Lc, Y scratch of
 // the same size; status |= 1 when a Cholesky pivot is not positive.
 osc_status dense_form_a(int s, int64_t nsys, const double *M, const double *K, double *Lc, double *Y, double *A,
@@ -138,6 +161,28 @@ osc_status dense_energy(int64_t batch, int s, int shared, const double *M, const
                         const double *dt, const T *x, const T *v, double *E, bool shadow, hipStream_t st);
 template <typename T>
 osc_status dense_launch_vec(const DenseLaunch<T> &a, int method, hipStream_t st);
+
+// Large-s dense path (dense_split.hip): two kernels per step over many
+// workgroups; state planes always in device memory.
+template <typename T>
+struct DenseSplitLaunch {
+    int64_t batch;
+    int32_t s;
+    int32_t shared;
+    const T *Bh, *Bl;
+    const double *h;
+    const T *x0, *v0;
+    T *state;                  // [4][batch][s]
+    T *P, *Q;                  // [batch][s] products (Verlet: P carried between steps)
+    int64_t *counter;          // completed steps (device)
+    int64_t nsteps, n0, out_stride;
+    T *xf, *vf, *xe, *ve;
+    int *nonfinite;
+    int load_mode, store_mode;
+};
+template <typename T>
+osc_status dense_split_run(const DenseSplitLaunch<T> &a, int method, hipStream_t st, hipGraphExec_t *graph,
+                           int64_t *graph_steps, int64_t graph_chunk);
 
 // Shared-operator MFMA path (dense_mfma.hip), FP32 state, s <= 256.
 struct DenseMfmaLaunch {
@@ -182,7 +227,12 @@ struct osc_sys {
     float inv_beta = 1.0f;
     double h_shared = 0.0;
     // configuration (osc_set_config)
-    int dense_kernel = 0;                // 0 auto, 1 VALU, 2 MFMA
+    int dense_kernel = 0;                // 0 auto, 1 VALU, 2 MFMA, 3 split
+    int64_t graph_steps = 64;            // steps per captured hipGraph (split path), 0 = eager
+    void *split_scratch = nullptr;       // P, Q planes and the step counter
+    hipGraphExec_t split_graph = nullptr;
+    int64_t split_graph_len = 0;
+    unsigned char split_key[256] = {};   // launch arguments the graph was captured with
     int64_t steps_per_launch = 0;        // 0: whole run in one launch
     void *state = nullptr;               // internal state planes for chunked runs
     size_t state_bytes = 0;

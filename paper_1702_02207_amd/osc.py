@@ -25,7 +25,7 @@ KINDS = {"chain": 0, "dense": 1}
 METHODS = {"rk4": 0, "verlet": 1}
 PRECS = {"f64": 0, "f32": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
-CFG_CHAIN_LAYOUT, CFG_DENSE_KERNEL, CFG_STEPS_PER_LAUNCH = 1, 2, 3
+CFG_CHAIN_LAYOUT, CFG_DENSE_KERNEL, CFG_STEPS_PER_LAUNCH, CFG_GRAPH_STEPS = 1, 2, 3, 4
 
 
 class OscError(RuntimeError):

@@ -151,3 +151,60 @@ def test_dense_mfma_and_valu_agree_and_chunking_is_bitwise(method):
     sysm.close()
     assert _err(whole[0], valu[0]).max() < 2 * TOL_F32
     assert _err(whole[1], valu[1]).max() < 2 * TOL_F32
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+@pytest.mark.parametrize("s,batch,shared", [(300, 1, True), (513, 2, False), (700, 1, True)])
+def test_dense_split_matches_oracle(method, prec, s, batch, shared):
+    """Large-s path: two kernels per step over many workgroups, replayed
+    from a captured hipGraph."""
+    import torch
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(500 + s, s, batch, 600, 100, shared=shared, vscale=0.01)
+    tdt = torch.float32 if prec == "f32" else torch.float64
+    sysm = osc.System("dense", method, prec, w.M, w.K, w.dt, shared=shared, batch=batch).create()
+    sysm.set_config(osc.CFG_DENSE_KERNEL, 3)
+    x0 = torch.as_tensor(w.x0, dtype=tdt, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=tdt, device="cuda")
+    xf, vf, xe, ve = [t.double().cpu().numpy() for t in sysm.integrate(x0, v0, 600, 100)]
+    sysm.sync()
+    sysm.close()
+    x0r, v0r = f32_inputs(w) if prec == "f32" else (w.x0, w.v0)
+    rx, rv, rxe, rve = oracle_dense(method, w, x0=x0r, v0=v0r)
+    tol = TOL_F32 if prec == "f32" else TOL_F64
+    assert _err(xf, rx).max() < tol
+    assert _err(vf, rv).max() < tol
+    assert _err(xe, rxe).max() < tol
+    assert _err(ve, rve).max() < tol
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_dense_split_graph_replays_match_eager(method):
+    """Every replay of the captured step graph, with other eager GPU work and
+    synchronisations in between, equals the eagerly launched run bitwise."""
+    import torch
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(901, 320, 2, 100, 10, shared=False, vscale=0.01)
+    sysm = osc.System("dense", method, "f32", w.M, w.K, w.dt, shared=False, batch=2,
+                      stream=torch.cuda.current_stream()).create()
+    sysm.set_config(osc.CFG_DENSE_KERNEL, 3)
+    x0 = torch.as_tensor(w.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=torch.float32, device="cuda")
+    sysm.set_config(osc.CFG_GRAPH_STEPS, 0)
+    ref = [t.cpu().numpy() for t in sysm.integrate(x0, v0, 100, 10)]
+    sysm.set_config(osc.CFG_GRAPH_STEPS, 16)
+    out = [torch.empty_like(t) for t in (torch.empty((11, 2, 320)), torch.empty((11, 2, 320)))]
+    xf = torch.empty((11, 2, 320), dtype=torch.float32, device="cuda")
+    vf = torch.empty_like(xf)
+    xe, ve = torch.empty_like(x0), torch.empty_like(v0)
+    for rep in range(4):
+        junk = torch.randn(1 << 20, device="cuda")
+        junk = (junk * 2.0).sum()                       # eager work between replays
+        torch.cuda.synchronize()
+        sysm.integrate(x0, v0, 100, 10, out=(xf, vf, xe, ve))
+        sysm.sync()
+        got = [t.cpu().numpy() for t in (xf, vf, xe, ve)]
+        for a, b in zip(ref, got):
+            np.testing.assert_array_equal(a, b)
+    sysm.close()
