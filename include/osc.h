@@ -195,6 +195,78 @@ const char *osc_last_error(void);
 /* osc_abi_version -- OSC_ABI_VERSION of the loaded library. */
 int osc_abi_version(void);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of single-instance integration requests.     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper proposes the oscillator model as a time-critical workload for
+ * hardware- and software-in-the-loop simulation and as a delay benchmark of
+ * parallel systems (introduction and conclusion).  A server runs many such
+ * integrations at once: requests of either kind, any s and step count are
+ * admitted, first come first served, while the bytes they hold on the device
+ * fit the HBM budget and a slot is free.  A worker thread then advances every
+ * admitted request by one chunk of time steps per scheduler iteration,
+ * batching requests of the same kernel shape into one work-list launch; a
+ * request that arrives while others run joins at the next iteration, and a
+ * finished one frees its memory and slot for the queue.  Chunk lengths depend
+ * only on the request itself, so every result is bitwise the same whether the
+ * request ran alone or in a mix.  Parameters and results are host arrays.
+ */
+typedef struct osc_server osc_server;
+
+typedef struct osc_server_config {
+    size_t hbm_budget;        /* device bytes the admitted requests may hold (0 = unlimited) */
+    int32_t max_slots;        /* requests admitted at once (>= 1) */
+    int32_t chunk_us;         /* target GPU time of one request chunk, microseconds (0 = 2000) */
+    int32_t fake_executor;    /* 1: no device work; chunks take simulated time (scheduler tests) */
+} osc_server_config;
+
+typedef struct osc_request_info {
+    osc_status status;        /* OSC_OK or the error that ended the request */
+    double queue_s;           /* submit -> admitted */
+    double latency_s;         /* submit -> results ready */
+    int64_t bytes;            /* device bytes accounted to the request */
+    int64_t iterations;       /* scheduler iterations the request took part in */
+} osc_request_info;
+
+typedef struct osc_server_counters {
+    int64_t submitted, completed, failed, queued, active;
+    int64_t iterations;
+    size_t hbm_in_use, hbm_peak;   /* accounted device bytes of admitted requests */
+} osc_server_counters;
+
+/* osc_server_create -- start a server (and its worker thread) on the current
+ * device.  cfg is copied. */
+osc_status osc_server_create(const osc_server_config *cfg, osc_server **out);
+
+/*
+ * osc_server_submit -- queue one integration.  desc describes one instance
+ * (batch must be 1; dense systems are given by their own M, K, shared = 1),
+ * with host parameters (param_mem = OSC_MEM_HOST); x0, v0 are host arrays of
+ * s elements of the request's precision.  Everything is copied before the call
+ * returns.  *ticket identifies the request.  OSC_ENOMEM if the request alone
+ * exceeds the budget, OSC_EBUSY after shutdown began.
+ */
+osc_status osc_server_submit(osc_server *srv, const osc_desc *desc, const void *x0, const void *v0,
+                             int64_t nsteps, int64_t out_stride, uint64_t *ticket);
+
+/*
+ * osc_server_wait -- wait up to timeout_s seconds (< 0: forever) for a
+ * request; on completion copy its results to the host arrays given (any may
+ * be NULL): frames [nframes][s], final state [s], and fill *info.  The request
+ * is forgotten after a successful wait.  OSC_ETIMEOUT if it is not done yet;
+ * the request's own error status otherwise.
+ */
+osc_status osc_server_wait(osc_server *srv, uint64_t ticket, double timeout_s, void *x_frames, void *v_frames,
+                           void *x_end, void *v_end, osc_request_info *info);
+
+/* osc_server_stats -- counters of the server so far. */
+osc_status osc_server_stats(osc_server *srv, osc_server_counters *out);
+
+/* osc_server_destroy -- finish the admitted requests, fail the queued ones,
+ * stop the worker and release everything.  NULL is a no-op. */
+void osc_server_destroy(osc_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -375,6 +375,26 @@ osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t n
 
 }  // namespace
 
+template <typename T>
+ChainCoef<T> chain_coef(const osc_sys *s) {
+    return coef_of<T>(s);
+}
+template ChainCoef<float> chain_coef<float>(const osc_sys *);
+template ChainCoef<double> chain_coef<double>(const osc_sys *);
+
+bool dense_uses_split(const osc_sys *s) { return use_split(s); }
+
+osc_status sys_ensure_state(osc_sys *s) { return ensure_state(s); }
+
+osc_status sys_ensure_split_scratch(osc_sys *s) {
+    const size_t n = (size_t)s->batch * s->s * (s->prec == OSC_F64 ? 8 : 4);
+    if (!s->split_scratch) {
+        s->split_scratch = pool_alloc(2 * n + 64);
+        if (!s->split_scratch) return fail(OSC_ENOMEM, "device memory exhausted for the split dense path");
+    }
+    return OSC_OK;
+}
+
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 osc_status fail(osc_status st, const std::string &msg) {

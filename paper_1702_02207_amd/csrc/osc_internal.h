@@ -9,6 +9,8 @@
 
 #include "osc.h"
 
+struct osc_sys;
+
 namespace osc {
 
 // ---------------------------------------------------------------------------
@@ -32,6 +34,7 @@ size_t pool_in_use();                    // bytes handed out and not yet returne
 size_t pool_budget();                    // 0 = unlimited
 void pool_set_budget(size_t bytes);
 void pool_trim();                        // return cached blocks to the device
+size_t pool_size_class(size_t bytes);    // bytes actually reserved for a request of this size
 
 // ---------------------------------------------------------------------------
 // chain integration (chain.hip)
@@ -203,6 +206,13 @@ int dense_mfma_pad(int s);                       // padded size (multiple of 64)
 size_t dense_mfma_fragment_elems(int s);         // FP16 elements per operator part
 osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *B1, _Float16 *B2, hipStream_t st);
 osc_status dense_mfma_launch(const DenseMfmaLaunch &a, int method, hipStream_t st);
+
+// runtime helpers shared by the server (api.hip)
+template <typename T>
+ChainCoef<T> chain_coef(const osc_sys *s);
+bool dense_uses_split(const osc_sys *s);
+osc_status sys_ensure_state(osc_sys *s);
+osc_status sys_ensure_split_scratch(osc_sys *s);
 
 }  // namespace osc
 

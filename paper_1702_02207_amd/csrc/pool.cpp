@@ -53,6 +53,8 @@ void trim_locked() {
 
 }  // namespace
 
+size_t pool_size_class(size_t bytes) { return size_class(bytes); }
+
 void *pool_alloc(size_t bytes) {
     const size_t c = size_class(bytes);
     int dev = 0;

@@ -1,0 +1,590 @@
+// Continuous-batching server for single-instance integration requests.
+//
+// A worker thread owns every device resource of the admitted requests.  Each
+// scheduler iteration it
+//   1. admits queued requests first come first served while the accounted
+//      device bytes stay within the HBM budget and a slot is free
+//      (allocation, parameter upload and operator formation happen here);
+//   2. advances every admitted request by one chunk of time steps: chains and
+//      small dense systems go into work-list launches, one per kernel shape,
+//      spread over four streams; large dense systems run their split path
+//      (captured step graphs) on a stream of their own;
+//   3. retires finished requests: results are copied to host memory, device
+//      memory and the slot are released, and waiters are woken.
+// A request's chunk length is a function of the request alone, and every
+// kernel computes an instance independently of its neighbours in a launch,
+// so results do not depend on what else is in flight.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "osc_internal.h"
+
+namespace osc {
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+enum class RState { QUEUED, ACTIVE, DONE, FAILED };
+
+struct Req {
+    uint64_t ticket = 0;
+    osc_desc desc{};
+    std::vector<double> M, K, dt;
+    std::vector<unsigned char> x0, v0;
+    int64_t nsteps = 0, out_stride = 0, nframes = 0;
+    size_t elem = 4;
+    int64_t bytes = 0;
+    RState st = RState::QUEUED;
+    osc_status status = OSC_OK;
+    std::string error;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int64_t iterations = 0;
+    // device side (worker thread only)
+    osc_sys *sys = nullptr;
+    void *dx0 = nullptr, *dv0 = nullptr, *dxf = nullptr, *dvf = nullptr, *dxe = nullptr, *dve = nullptr;
+    bool split = false;
+    int64_t done = 0, chunk = 0;
+    // results
+    std::vector<unsigned char> hxf, hvf, hxe, hve;
+};
+
+constexpr int kStreams = 4;
+
+// Conservative device bytes of a request: every allocation rounded to the
+// pool's size classes.
+int64_t estimate_bytes(const osc_desc &d, int64_t nframes) {
+    const size_t e = d.prec == OSC_F64 ? 8 : 4;
+    const size_t s = (size_t)d.s;
+    size_t b = 0;
+    auto add = [&](size_t n) { b += pool_size_class(n); };
+    add(s * e); add(s * e); add(s * e); add(s * e);              // x0, v0, x_end, v_end
+    if (nframes > 0) { add(nframes * s * e); add(nframes * s * e); }
+    add(4 * s * e + 4);                                          // chunked-run state
+    add(64);                                                     // non-finite flag
+    if (d.kind == OSC_CHAIN) {
+        add(s * 8); add(s * 8); add(8);                          // m, k, h
+        add((d.prec == OSC_F32 ? 4 : 2) * s * e);                // coefficients
+        add(64);                                                 // create scratch
+    } else {
+        const size_t ss = s * s;
+        add(ss * 8); add(ss * 8); add(ss * 8); add(8);           // M, K, A, h
+        add(ss * e); if (d.prec == OSC_F32) add(ss * e);         // B hi / lo
+        add(ss * 8); add(ss * 8); add(64); add(8);               // create temporaries
+        if (d.prec == OSC_F32 && s <= 256) {                     // MFMA fragments
+            const size_t fe = dense_mfma_fragment_elems((int)s) * 2;
+            add(fe); add(fe);
+        }
+        add(2 * s * e + 64);                                     // split scratch
+    }
+    return (int64_t)b;
+}
+
+// Estimated seconds per step of one instance, used only to size chunks.
+double step_seconds(const Req &r) {
+    const double s = r.desc.s;
+    if (r.desc.kind == OSC_CHAIN) return 2e-7 + 4e-9 * s;
+    if (r.split) return 1.5e-5 + 1e-12 * s * s;
+    return 1e-6 + 2e-10 * s * s;
+}
+
+struct Server {
+    osc_server_config cfg{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::map<uint64_t, Req *> all;
+    std::atomic<uint64_t> next_ticket{1};
+    bool stopping = false;
+    size_t in_use = 0, peak = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, iterations = 0;
+    std::thread worker;
+    hipStream_t streams[kStreams] = {};
+    void *stage = nullptr;       // pinned host staging of work lists
+    size_t stage_bytes = 0;
+    void *items = nullptr;       // device copy of work lists
+    size_t items_bytes = 0;
+
+    void loop();
+    void setup(Req *r);
+    void run_iteration(std::vector<Req *> &act);
+    void finish(Req *r, osc_status st, const std::string &msg);
+    void release_device(Req *r);
+    template <typename T>
+    void launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt);
+};
+
+void Server::release_device(Req *r) {
+    for (void *p : {r->dx0, r->dv0, r->dxf, r->dvf, r->dxe, r->dve}) pool_free(p);
+    r->dx0 = r->dv0 = r->dxf = r->dvf = r->dxe = r->dve = nullptr;
+    if (r->sys) osc_destroy(r->sys);
+    r->sys = nullptr;
+}
+
+void Server::finish(Req *r, osc_status st, const std::string &msg) {
+    if (!cfg.fake_executor) release_device(r);
+    std::lock_guard<std::mutex> lk(mu);
+    r->status = st;
+    r->error = msg;
+    r->t_done = now_s();
+    r->st = st == OSC_OK ? RState::DONE : RState::FAILED;
+    in_use -= (size_t)r->bytes;
+    if (st == OSC_OK) ++completed;
+    else ++failed;
+    active.erase(std::remove(active.begin(), active.end(), r), active.end());
+    cv_done.notify_all();
+}
+
+void Server::setup(Req *r) {
+    const size_t s = (size_t)r->desc.s;
+    r->hxe.assign(s * r->elem, 0);
+    r->hve.assign(s * r->elem, 0);
+    r->hxf.assign(r->nframes * s * r->elem, 0);
+    r->hvf.assign(r->nframes * s * r->elem, 0);
+    if (cfg.fake_executor) {
+        r->chunk = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(*r)));
+        return;
+    }
+    osc_desc d = r->desc;
+    d.M = r->M.data();
+    d.K = r->K.data();
+    d.dt = r->dt.data();
+    d.param_mem = OSC_MEM_HOST;
+    osc_status st = osc_create(&d, streams[0], &r->sys);
+    if (st != OSC_OK) {
+        finish(r, st, osc_last_error());
+        return;
+    }
+    r->dx0 = pool_alloc(s * r->elem);
+    r->dv0 = pool_alloc(s * r->elem);
+    r->dxe = pool_alloc(s * r->elem);
+    r->dve = pool_alloc(s * r->elem);
+    if (r->nframes > 0) {
+        r->dxf = pool_alloc(r->nframes * s * r->elem);
+        r->dvf = pool_alloc(r->nframes * s * r->elem);
+    }
+    r->split = r->desc.kind == OSC_DENSE && dense_uses_split(r->sys);
+    st = sys_ensure_state(r->sys);
+    if (st == OSC_OK && r->split) st = sys_ensure_split_scratch(r->sys);
+    if (st != OSC_OK || !r->dx0 || !r->dv0 || !r->dxe || !r->dve || (r->nframes > 0 && (!r->dxf || !r->dvf))) {
+        finish(r, OSC_ENOMEM, "device memory exhausted while admitting a request");
+        return;
+    }
+    if (hipMemcpyAsync(r->dx0, r->x0.data(), s * r->elem, hipMemcpyHostToDevice, streams[0]) != hipSuccess ||
+        hipMemcpyAsync(r->dv0, r->v0.data(), s * r->elem, hipMemcpyHostToDevice, streams[0]) != hipSuccess ||
+        hipStreamSynchronize(streams[0]) != hipSuccess) {
+        finish(r, OSC_EDEVICE, "upload of the initial state failed");
+        return;
+    }
+    r->chunk = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(*r)));
+    if (r->split) r->chunk = std::max<int64_t>(64, r->chunk / 64 * 64);   // whole captured graphs
+}
+
+// Build, upload and launch the work lists of one precision.
+template <typename T>
+void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
+    std::map<std::pair<int, int64_t>, std::vector<ChainItem<T>>> chains;   // (method, layout)
+    std::map<std::pair<int, int>, std::vector<DenseItem<T>>> denses;       // (method, smax bucket)
+    std::map<std::pair<int, int>, int> dense_smax;
+    const size_t want_elem = sizeof(T);
+    int next_stream = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+        Req *r = act[i];
+        if (r->elem != want_elem || !r->sys) continue;
+        const int64_t n0 = r->done, c = cnt[i];
+        const int load = n0 == 0 ? LOAD_USER : LOAD_STATE;
+        const int store = n0 + c == r->nsteps ? STORE_USER : STORE_STATE;
+        osc_sys *sy = r->sys;
+        if (r->desc.kind == OSC_CHAIN) {
+            ChainItem<T> it{};
+            it.L.batch = 1;
+            it.L.s = sy->s;
+            it.L.c = chain_coef<T>(sy);
+            it.L.x0 = static_cast<const T *>(r->dx0);
+            it.L.v0 = static_cast<const T *>(r->dv0);
+            it.L.state = static_cast<T *>(sy->state);
+            it.L.nsteps = c;
+            it.L.n0 = n0;
+            it.L.out_stride = r->out_stride;
+            it.L.xf = static_cast<T *>(r->dxf);
+            it.L.vf = static_cast<T *>(r->dvf);
+            it.L.xe = static_cast<T *>(r->dxe);
+            it.L.ve = static_cast<T *>(r->dve);
+            it.L.nonfinite = sy->flag;
+            it.L.load_mode = load;
+            it.L.store_mode = store;
+            it.b = 0;
+            const int64_t key = ((int64_t)sy->cfg.lpi << 16) | sy->cfg.dpl;
+            chains[{(int)sy->method, key}].push_back(it);
+        } else if (!r->split) {
+            DenseItem<T> it{};
+            it.L.batch = 1;
+            it.L.s = sy->s;
+            it.L.shared = 1;
+            it.L.Bh = static_cast<const T *>(sy->Bh);
+            it.L.Bl = static_cast<const T *>(sy->Bl);
+            it.L.h = sy->h;
+            it.L.x0 = static_cast<const T *>(r->dx0);
+            it.L.v0 = static_cast<const T *>(r->dv0);
+            it.L.state = static_cast<T *>(sy->state);
+            it.L.nsteps = c;
+            it.L.n0 = n0;
+            it.L.out_stride = r->out_stride;
+            it.L.xf = static_cast<T *>(r->dxf);
+            it.L.vf = static_cast<T *>(r->dvf);
+            it.L.xe = static_cast<T *>(r->dxe);
+            it.L.ve = static_cast<T *>(r->dve);
+            it.L.nonfinite = sy->flag;
+            it.L.load_mode = load;
+            it.L.store_mode = store;
+            it.b = 0;
+            const std::pair<int, int> key{(int)sy->method, dense_vec_bucket(sy->s)};
+            denses[key].push_back(it);
+            dense_smax[key] = std::max(dense_smax[key], (int)sy->s);
+        } else {
+            DenseSplitLaunch<T> a{};
+            a.batch = 1;
+            a.s = sy->s;
+            a.shared = 1;
+            a.Bh = static_cast<const T *>(sy->Bh);
+            a.Bl = static_cast<const T *>(sy->Bl);
+            a.h = sy->h;
+            a.state = static_cast<T *>(sy->state);
+            a.P = static_cast<T *>(sy->split_scratch);
+            a.Q = a.P + sy->s;
+            a.counter = reinterpret_cast<int64_t *>(a.Q + sy->s);
+            a.out_stride = r->out_stride;
+            a.xf = static_cast<T *>(r->dxf);
+            a.vf = static_cast<T *>(r->dvf);
+            a.nonfinite = sy->flag;
+            a.x0 = static_cast<const T *>(r->dx0);
+            a.v0 = static_cast<const T *>(r->dv0);
+            a.xe = static_cast<T *>(r->dxe);
+            a.ve = static_cast<T *>(r->dve);
+            a.n0 = n0;
+            a.nsteps = c;
+            a.load_mode = load;
+            a.store_mode = store;
+            // the step graph's arguments do not change between chunks of a request
+            osc_status st = dense_split_run<T>(a, sy->method, streams[next_stream], &sy->split_graph,
+                                               &sy->split_graph_len, 64);
+            next_stream = (next_stream + 1) % kStreams;
+            if (st != OSC_OK) r->status = st;
+        }
+    }
+    // upload all work lists in one copy, then launch them across the streams
+    size_t bytes = 0;
+    for (auto &g : chains) bytes += (g.second.size() * sizeof(ChainItem<T>) + 255) / 256 * 256;
+    for (auto &g : denses) bytes += (g.second.size() * sizeof(DenseItem<T>) + 255) / 256 * 256;
+    if (bytes == 0) return;
+    if (bytes > stage_bytes) {
+        if (stage) (void)hipHostFree(stage);
+        pool_free(items);
+        stage_bytes = bytes * 2;
+        if (hipHostMalloc(&stage, stage_bytes, 0) != hipSuccess) stage = nullptr;
+        items = pool_alloc(stage_bytes);
+        items_bytes = stage_bytes;
+        if (!stage || !items) {
+            for (Req *r : act) r->status = OSC_ENOMEM;
+            stage_bytes = 0;
+            return;
+        }
+    }
+    size_t off = 0;
+    std::vector<std::pair<size_t, size_t>> spans;
+    for (auto &g : chains) {
+        std::memcpy(static_cast<char *>(stage) + off, g.second.data(), g.second.size() * sizeof(ChainItem<T>));
+        spans.push_back({off, g.second.size()});
+        off += (g.second.size() * sizeof(ChainItem<T>) + 255) / 256 * 256;
+    }
+    for (auto &g : denses) {
+        std::memcpy(static_cast<char *>(stage) + off, g.second.data(), g.second.size() * sizeof(DenseItem<T>));
+        spans.push_back({off, g.second.size()});
+        off += (g.second.size() * sizeof(DenseItem<T>) + 255) / 256 * 256;
+    }
+    hipEvent_t ready;
+    (void)hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    (void)hipMemcpyAsync(items, stage, off, hipMemcpyHostToDevice, streams[0]);
+    (void)hipEventRecord(ready, streams[0]);
+    size_t k = 0;
+    for (auto &g : chains) {
+        hipStream_t st = streams[next_stream];
+        next_stream = (next_stream + 1) % kStreams;
+        (void)hipStreamWaitEvent(st, ready, 0);
+        const ChainConfig cfgc{(int)(g.first.second >> 16), (int)(g.first.second & 0xffff)};
+        (void)chain_launch_items<T>(reinterpret_cast<const ChainItem<T> *>(static_cast<char *>(items) + spans[k].first),
+                                    (int64_t)spans[k].second, g.first.first, cfgc, st);
+        ++k;
+    }
+    for (auto &g : denses) {
+        hipStream_t st = streams[next_stream];
+        next_stream = (next_stream + 1) % kStreams;
+        (void)hipStreamWaitEvent(st, ready, 0);
+        (void)dense_launch_items<T>(reinterpret_cast<const DenseItem<T> *>(static_cast<char *>(items) + spans[k].first),
+                                    (int64_t)spans[k].second, dense_smax[g.first], g.first.first, st);
+        ++k;
+    }
+    (void)hipEventDestroy(ready);
+}
+
+void Server::run_iteration(std::vector<Req *> &act) {
+    std::vector<int64_t> cnt(act.size());
+    double sim = 0.0;
+    for (size_t i = 0; i < act.size(); ++i) {
+        cnt[i] = std::min(act[i]->chunk, act[i]->nsteps - act[i]->done);
+        sim = std::max(sim, cnt[i] * step_seconds(*act[i]));
+    }
+    if (cfg.fake_executor) {
+        std::this_thread::sleep_for(std::chrono::duration<double>(std::min(sim, 0.002)));
+    } else {
+        launch_groups<float>(act, cnt);
+        launch_groups<double>(act, cnt);
+        for (auto &st : streams) (void)hipStreamSynchronize(st);
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        ++iterations;
+    }
+    for (size_t i = 0; i < act.size(); ++i) {
+        Req *r = act[i];
+        r->done += cnt[i];
+        ++r->iterations;
+        if (r->status != OSC_OK) {
+            finish(r, r->status, "a launch of this request failed");
+            continue;
+        }
+        if (r->done < r->nsteps) continue;
+        osc_status st = OSC_OK;
+        std::string msg;
+        if (!cfg.fake_executor) {
+            const size_t s = (size_t)r->desc.s;
+            bool ok = hipMemcpy(r->hxe.data(), r->dxe, s * r->elem, hipMemcpyDeviceToHost) == hipSuccess &&
+                      hipMemcpy(r->hve.data(), r->dve, s * r->elem, hipMemcpyDeviceToHost) == hipSuccess;
+            if (r->nframes > 0)
+                ok = ok &&
+                     hipMemcpy(r->hxf.data(), r->dxf, r->nframes * s * r->elem, hipMemcpyDeviceToHost) == hipSuccess &&
+                     hipMemcpy(r->hvf.data(), r->dvf, r->nframes * s * r->elem, hipMemcpyDeviceToHost) == hipSuccess;
+            if (!ok) {
+                st = OSC_EDEVICE;
+                msg = "download of the results failed";
+            } else {
+                st = osc_sync(r->sys);
+                if (st != OSC_OK) msg = osc_last_error();
+            }
+        } else {
+            std::memcpy(r->hxe.data(), r->x0.data(), r->x0.size());
+            std::memcpy(r->hve.data(), r->v0.data(), r->v0.size());
+        }
+        finish(r, st, msg);
+    }
+}
+
+void Server::loop() {
+    if (!cfg.fake_executor) (void)hipSetDevice(device);
+    for (;;) {
+        std::vector<Req *> admitted, act;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            while (!queue.empty() && (int)active.size() < cfg.max_slots) {
+                Req *r = queue.front();
+                if (cfg.hbm_budget && in_use + (size_t)r->bytes > cfg.hbm_budget) break;   // wait for memory
+                queue.pop_front();
+                in_use += (size_t)r->bytes;
+                peak = std::max(peak, in_use);
+                r->st = RState::ACTIVE;
+                r->t_admit = now_s();
+                active.push_back(r);
+                admitted.push_back(r);
+            }
+            if (admitted.empty() && active.empty()) {
+                if (stopping) break;
+                cv_work.wait_for(lk, std::chrono::milliseconds(20));
+                continue;
+            }
+        }
+        for (Req *r : admitted) setup(r);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            act = active;
+        }
+        if (!act.empty()) run_iteration(act);
+    }
+}
+
+}  // namespace
+}  // namespace osc
+
+struct osc_server {
+    osc::Server impl;
+};
+
+using namespace osc;
+
+extern "C" {
+
+osc_status osc_server_create(const osc_server_config *cfg, osc_server **out) {
+    if (!out) return fail(OSC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(OSC_EINVAL, "config is NULL");
+    if (cfg->max_slots < 1) return fail(OSC_EINVAL, "max_slots must be >= 1");
+    if (cfg->chunk_us < 0) return fail(OSC_EINVAL, "chunk_us must be >= 0");
+    osc_server *srv = new (std::nothrow) osc_server();
+    if (!srv) return fail(OSC_ENOMEM, "host allocation failed");
+    Server &S = srv->impl;
+    S.cfg = *cfg;
+    if (S.cfg.chunk_us == 0) S.cfg.chunk_us = 2000;
+    if (!S.cfg.fake_executor) {
+        if (hipGetDevice(&S.device) != hipSuccess) {
+            delete srv;
+            return fail(OSC_EDEVICE, "no HIP device");
+        }
+        for (auto &st : S.streams) {
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                for (auto &t : S.streams)
+                    if (t) (void)hipStreamDestroy(t);
+                delete srv;
+                return fail(OSC_EDEVICE, "stream creation failed");
+            }
+        }
+    }
+    S.worker = std::thread([&S] { S.loop(); });
+    *out = srv;
+    return OSC_OK;
+}
+
+osc_status osc_server_submit(osc_server *srv, const osc_desc *d, const void *x0, const void *v0, int64_t nsteps,
+                             int64_t out_stride, uint64_t *ticket) {
+    if (!srv || !d || !x0 || !v0 || !ticket) return fail(OSC_EINVAL, "NULL argument");
+    if (d->batch != 1) return fail(OSC_EINVAL, "a request is one instance (batch = 1)");
+    if (d->param_mem != OSC_MEM_HOST) return fail(OSC_EINVAL, "request parameters must be host arrays");
+    if (d->s < 1 || d->s > 2048) return fail(OSC_EINVAL, "s must be in [1, 2048]");
+    if (d->kind != OSC_CHAIN && d->kind != OSC_DENSE) return fail(OSC_EINVAL, "unknown kind");
+    if (d->method != OSC_RK4 && d->method != OSC_VERLET) return fail(OSC_EINVAL, "unknown method");
+    if (d->prec != OSC_F64 && d->prec != OSC_F32) return fail(OSC_EINVAL, "unknown precision");
+    if (!d->M || !d->K || !d->dt) return fail(OSC_EINVAL, "M, K and dt must be non-NULL");
+    if (nsteps < 0 || out_stride < 0) return fail(OSC_EINVAL, "nsteps and out_stride must be >= 0");
+    Server &S = srv->impl;
+    Req *r = new (std::nothrow) Req();
+    if (!r) return fail(OSC_ENOMEM, "host allocation failed");
+    const size_t s = (size_t)d->s;
+    r->desc = *d;
+    r->desc.shared = d->kind == OSC_DENSE ? 1 : 0;
+    const size_t np = d->kind == OSC_CHAIN ? s : s * s;
+    r->M.assign(d->M, d->M + np);
+    r->K.assign(d->K, d->K + np);
+    r->dt.assign(d->dt, d->dt + 1);
+    r->elem = d->prec == OSC_F64 ? 8 : 4;
+    r->x0.assign(static_cast<const unsigned char *>(x0), static_cast<const unsigned char *>(x0) + s * r->elem);
+    r->v0.assign(static_cast<const unsigned char *>(v0), static_cast<const unsigned char *>(v0) + s * r->elem);
+    r->nsteps = nsteps;
+    r->out_stride = out_stride;
+    r->nframes = out_stride > 0 ? nsteps / out_stride + 1 : 0;
+    r->bytes = estimate_bytes(r->desc, r->nframes);
+    if (S.cfg.hbm_budget && (size_t)r->bytes > S.cfg.hbm_budget) {
+        delete r;
+        return fail(OSC_ENOMEM, "request needs more device memory than the whole budget");
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.stopping) {
+        delete r;
+        return fail(OSC_EBUSY, "server is shutting down");
+    }
+    r->ticket = S.next_ticket++;
+    r->t_submit = now_s();
+    S.queue.push_back(r);
+    S.all[r->ticket] = r;
+    ++S.submitted;
+    *ticket = r->ticket;
+    S.cv_work.notify_one();
+    return OSC_OK;
+}
+
+osc_status osc_server_wait(osc_server *srv, uint64_t ticket, double timeout_s, void *xf, void *vf, void *xe,
+                           void *ve, osc_request_info *info) {
+    if (!srv) return fail(OSC_EINVAL, "server is NULL");
+    Server &S = srv->impl;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto it = S.all.find(ticket);
+    if (it == S.all.end()) return fail(OSC_EINVAL, "unknown ticket");
+    Req *r = it->second;
+    auto done = [&] { return r->st == RState::DONE || r->st == RState::FAILED; };
+    if (timeout_s < 0) S.cv_done.wait(lk, done);
+    else if (!S.cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done))
+        return fail(OSC_ETIMEOUT, "request not finished yet");
+    if (info) {
+        info->status = r->status;
+        info->queue_s = r->t_admit > 0 ? r->t_admit - r->t_submit : r->t_done - r->t_submit;
+        info->latency_s = r->t_done - r->t_submit;
+        info->bytes = r->bytes;
+        info->iterations = r->iterations;
+    }
+    const osc_status st = r->status;
+    if (st == OSC_OK) {
+        if (xf && !r->hxf.empty()) std::memcpy(xf, r->hxf.data(), r->hxf.size());
+        if (vf && !r->hvf.empty()) std::memcpy(vf, r->hvf.data(), r->hvf.size());
+        if (xe) std::memcpy(xe, r->hxe.data(), r->hxe.size());
+        if (ve) std::memcpy(ve, r->hve.data(), r->hve.size());
+    }
+    const std::string msg = r->error;
+    S.all.erase(it);
+    delete r;
+    if (st != OSC_OK) return fail(st, msg.empty() ? "request failed" : msg);
+    return OSC_OK;
+}
+
+osc_status osc_server_stats(osc_server *srv, osc_server_counters *out) {
+    if (!srv || !out) return fail(OSC_EINVAL, "NULL argument");
+    Server &S = srv->impl;
+    std::lock_guard<std::mutex> lk(S.mu);
+    out->submitted = S.submitted;
+    out->completed = S.completed;
+    out->failed = S.failed;
+    out->queued = (int64_t)S.queue.size();
+    out->active = (int64_t)S.active.size();
+    out->iterations = S.iterations;
+    out->hbm_in_use = S.in_use;
+    out->hbm_peak = S.peak;
+    return OSC_OK;
+}
+
+void osc_server_destroy(osc_server *srv) {
+    if (!srv) return;
+    Server &S = srv->impl;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.stopping = true;
+        for (Req *r : S.queue) {
+            r->st = RState::FAILED;
+            r->status = OSC_EBUSY;
+            r->error = "server shut down before the request was admitted";
+            r->t_done = now_s();
+            ++S.failed;
+        }
+        S.queue.clear();
+        S.cv_work.notify_all();
+        S.cv_done.notify_all();
+    }
+    if (S.worker.joinable()) S.worker.join();
+    for (auto &kv : S.all) delete kv.second;
+    S.all.clear();
+    if (S.stage) (void)hipHostFree(S.stage);
+    pool_free(S.items);
+    for (auto &st : S.streams)
+        if (st) (void)hipStreamDestroy(st);
+    delete srv;
+}
+
+}  // extern "C"

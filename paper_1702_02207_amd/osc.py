@@ -41,6 +41,22 @@ class Desc(ctypes.Structure):
                 ("dt", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("chunk_us", ctypes.c_int32), ("fake_executor", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double),
+                ("bytes", ctypes.c_int64), ("iterations", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("active", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -62,6 +78,13 @@ def load():
         "osc_sync": (i32, [vp]),
         "osc_dense_operator": (i32, [vp, vp]),
         "osc_set_config": (i32, [vp, i32, i64]),
+        "osc_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+        "osc_server_submit": (i32, [vp, ctypes.POINTER(Desc), vp, vp, i64, i64,
+                                    ctypes.POINTER(ctypes.c_uint64)]),
+        "osc_server_wait": (i32, [vp, ctypes.c_uint64, ctypes.c_double, vp, vp, vp, vp,
+                                  ctypes.POINTER(RequestInfo)]),
+        "osc_server_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
+        "osc_server_destroy": (None, [vp]),
         "osc_destroy": (None, [vp]),
         "osc_last_error": (ctypes.c_char_p, []),
         "osc_abi_version": (i32, []),
@@ -220,3 +243,71 @@ class System:
 
 def chain_system(method: str, prec: str, m, k, dt, stream=None) -> System:
     return System("chain", method, prec, m, k, dt, stream=stream).create()
+
+
+class Server:
+    """Continuous-batching request server (osc_server_*).  Requests are single
+    instances given as host numpy arrays; results come back as numpy arrays."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 256, chunk_us: int = 0,
+                 fake_executor: bool = False):
+        lib = load()
+        cfg = ServerConfig(int(hbm_budget), int(max_slots), int(chunk_us), 1 if fake_executor else 0)
+        h = ctypes.c_void_p()
+        _check(lib.osc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._meta = {}
+
+    def submit(self, kind: str, method: str, prec: str, M, K, dt, x0, v0, nsteps: int,
+               out_stride: int = 0) -> int:
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        dt = np.ascontiguousarray(np.atleast_1d(dt), dtype=np.float64)
+        dtype = np.float64 if prec == "f64" else np.float32
+        x0 = np.ascontiguousarray(np.ravel(x0), dtype=dtype)
+        v0 = np.ascontiguousarray(np.ravel(v0), dtype=dtype)
+        s = x0.shape[0]
+        d = Desc(KINDS[kind], METHODS[method], PRECS[prec], s, 1, 1 if kind == "dense" else 0,
+                 MEM_HOST, M.ctypes.data, K.ctypes.data, dt.ctypes.data)
+        t = ctypes.c_uint64()
+        _check(load().osc_server_submit(self.handle, ctypes.byref(d), x0.ctypes.data, v0.ctypes.data,
+                                        int(nsteps), int(out_stride), ctypes.byref(t)))
+        nf = nsteps // out_stride + 1 if out_stride > 0 else 0
+        self._meta[t.value] = (s, nf, dtype)
+        return t.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """Returns dict(x_frames, v_frames, x_end, v_end, info) or raises OscError
+        (OSC_ETIMEOUT if not done within timeout seconds)."""
+        s, nf, dtype = self._meta.get(ticket, (0, 0, np.float32))
+        xf = np.empty((nf, s), dtype=dtype)
+        vf = np.empty((nf, s), dtype=dtype)
+        xe = np.empty(s, dtype=dtype)
+        ve = np.empty(s, dtype=dtype)
+        info = RequestInfo()
+        st = load().osc_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout),
+                                    xf.ctypes.data if nf else None, vf.ctypes.data if nf else None,
+                                    xe.ctypes.data, ve.ctypes.data, ctypes.byref(info))
+        if st == OSC_ETIMEOUT:
+            _check(st)
+        self._meta.pop(ticket, None)
+        _check(st)
+        return {"x_frames": xf, "v_frames": vf, "x_end": xe, "v_end": ve,
+                "latency_s": info.latency_s, "queue_s": info.queue_s, "bytes": info.bytes,
+                "iterations": info.iterations}
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().osc_server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle is not None:
+            load().osc_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

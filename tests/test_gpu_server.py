@@ -1,0 +1,86 @@
+"""GPU tests of the request server: results match the FP64 oracle, each
+request's result is bitwise the same alone and in a mix, and late arrivals
+are admitted while earlier requests run."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_02207_amd import osc, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(n, seed, s_max=600, nsteps=(200, 3000)):
+    return workloads.c5_request_stream(n_requests=n, qps=1e6, s_max=s_max, nsteps_range=nsteps,
+                                       seed_salt=seed)
+
+
+def _submit(srv, req, method="rk4"):
+    w = req.system
+    if req.kind == "chain":
+        return srv.submit("chain", method, "f32", w.m[0], w.k[0], w.dt, w.x0[0], w.v0[0], w.nsteps, w.out_stride)
+    return srv.submit("dense", method, "f32", w.M, w.K, w.dt, w.x0[0], w.v0[0], w.nsteps, w.out_stride)
+
+
+def _oracle(req, method="rk4"):
+    w = req.system
+    x0 = w.x0.astype(np.float32).astype(np.float64)
+    v0 = w.v0.astype(np.float32).astype(np.float64)
+    if req.kind == "chain":
+        xf, vf, _, _ = oracle.chain(method, w.m, w.k, w.dt, x0, v0, w.nsteps, w.out_stride)
+    else:
+        xf, vf, _, _ = oracle.dense(method, w.M, w.K, w.dt, x0, v0, w.nsteps, w.out_stride)
+    return xf[:, 0], vf[:, 0]
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_served_results_match_oracle_and_are_identical_alone_and_in_mix(method):
+    reqs = _stream(20, seed=11)
+    with osc.Server(max_slots=64, chunk_us=500) as srv:
+        tickets = [_submit(srv, r, method) for r in reqs]
+        mixed = [srv.wait(t, timeout=120.0) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for r, res in zip(reqs, mixed):
+        rx, rv = _oracle(r, method)
+        ex = oracle.rel_traj_err(res["x_frames"][:, None, :], rx[:, None, :])[0]
+        ev = oracle.rel_traj_err(res["v_frames"][:, None, :], rv[:, None, :])[0]
+        assert ex < 1e-5 and ev < 1e-5, (r.kind, r.system.s, ex, ev)
+    # each request alone on a fresh server
+    for i in (0, 3, 7, 12, 19):
+        with osc.Server(max_slots=4, chunk_us=500) as srv:
+            alone = srv.wait(_submit(srv, reqs[i], method), timeout=120.0)
+        for key in ("x_frames", "v_frames", "x_end", "v_end"):
+            np.testing.assert_array_equal(alone[key], mixed[i][key])
+
+
+def test_budget_respected_on_device():
+    reqs = _stream(16, seed=5, s_max=300)
+    with osc.Server(max_slots=64) as srv:
+        sizes = [srv.wait(t, timeout=120.0)["bytes"] for t in [_submit(srv, r) for r in reqs]]
+    budget = 2 * max(sizes) + (1 << 20)      # at most a few requests fit at once
+    with osc.Server(hbm_budget=budget, max_slots=64) as srv:
+        tickets = [_submit(srv, r) for r in reqs]
+        for t in tickets:
+            srv.wait(t, timeout=120.0)
+        st = srv.stats()
+    assert st["completed"] == len(reqs)
+    assert max(sizes) <= st["hbm_peak"] <= budget
+
+
+def test_continuous_admission():
+    rng = np.random.default_rng(9)
+    s = 512
+    m = rng.uniform(0.5, 2.0, s)
+    k = np.exp(rng.uniform(np.log(1e2), np.log(1e4), s))
+    dt = 0.01 / workloads.chain_omega_max(m[None], k[None])
+    with osc.Server(max_slots=16, chunk_us=1000) as srv:
+        long_t = srv.submit("chain", "rk4", "f32", m, k, dt, rng.normal(0, 0.1, s), np.zeros(s), 400_000, 0)
+        import time
+        time.sleep(0.05)
+        short_t = srv.submit("chain", "rk4", "f32", m, k, dt, rng.normal(0, 0.1, s), np.zeros(s), 1000, 0)
+        short = srv.wait(short_t, timeout=60.0)
+        st = srv.stats()
+        assert st["active"] >= 1            # the long request is still running
+        long = srv.wait(long_t, timeout=120.0)
+    assert short["latency_s"] < long["latency_s"]
