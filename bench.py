@@ -1,21 +1,25 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the batched oscillator integrator on one MI355X.
 
-Default workload: 2^20 independent two-mass systems (eq. (2)), m1, m2 ~
+Default workload (c2): 2^20 independent two-mass systems (eq. (2)), m1, m2 ~
 LogU[0.5, 5], C1, C2 ~ LogU[1e2, 1e4], x0, v0 ~ N(0, 1), dt = 0.01/omega_max,
 10^4 classic RK4 steps with FP32 state (synthetic, seeded).
 
 One timed step is one pass of the whole hot path over the batch, with every
 input already resident in HBM: osc_create from device-resident FP64
-parameters (coefficients h^2 k/m split into FP32 hi + lo, stability bound),
-osc_integrate (all 10^4 steps, frames at n = 0 and n = nsteps), osc_energy
-(FP64 energy of the final state), osc_sync and osc_destroy.
+parameters (chains: coefficients h^2 k/m split into FP32 hi + lo and the
+stability bound; dense: A = M^-1 K by FP64 Cholesky, the bound and the split
+FP16 operator), osc_integrate (every step of the run, frames at n = 0 and
+n = nsteps unless stated), osc_energy (FP64 energy of the final state),
+osc_sync and osc_destroy.
 
-Printed JSON line (rank 0): value = DOF-steps/s = batch * s * nsteps / step
-time.  Also reported: the plain per-instance GPU integrator (one step per
-launch) on a sample and the speedup over it, the roofline of the dominant
-kernel, the FP64 oracle timed on the host cores on a bounded sample, and the
-max relative trajectory error of the sampled instances against that oracle.
+Printed JSON line: value = DOF-steps/s = batch * s * nsteps / step time.  Also
+reported: the plain per-instance GPU integrator (one instance at a time, one
+time step per launch) on a sample and the speedup over it, the roofline of the
+dominant kernel (live HIP-event timing of its launch), the FP64 oracle timed
+on the host cores on a bounded sample, and the max relative trajectory error
+of those sampled instances against the oracle.  --workload c5 runs the
+request server instead (p50/p99 latency and DOF-steps/s).
 """
 from __future__ import annotations
 
@@ -29,26 +33,37 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32 vector (published)
-PEAK_FP64_TFLOPS = 78.6
+PEAK = {"fp32": 157.3, "fp64": 78.6, "fp16_mfma": 2500.0}   # MI355X published, TFLOP/s
 TOL = {"f32": 1e-5, "f64": 1e-10}
 
-# Algorithmic FP32 flops per DOF-step of the integrator arithmetic at the
-# target precision (FMA = 2 flops): RK4 four B-products (B x with split
-# coefficients 8, three others 4 each), two update polynomials (6 each) and
-# two compensated sums (4 each) = 40; Verlet leapfrog: B x split 8, two
-# compensated sums 4 each = 16.
-FLOPS_PER_DOF_STEP = {"rk4": 40, "verlet": 16}
+# Algorithmic flops per DOF-step (FMA = 2).  Chains, at the FP32 target
+# precision: RK4 = four B-products (B x with split coefficients 8, three
+# others 4 each), two update polynomials (6 each), two compensated sums (4
+# each) = 40; Verlet leapfrog = split B x 8 + two compensated sums = 16.
+# FP64 chains drop the split and compensation: RK4 28, Verlet 8.  Dense
+# (one operator shared by the batch): the products alone, RK4 4 x 2s, Verlet
+# 1 x 2s (the split FP16 terms the hardware runs are reported separately).
+CHAIN_FLOPS = {("rk4", "f32"): 40, ("verlet", "f32"): 16, ("rk4", "f64"): 28, ("verlet", "f64"): 8}
+DENSE_PRODUCTS = {"rk4": 4, "verlet": 1}
+DENSE_HW_TERMS = {"rk4": 9, "verlet": 3}     # MFMA products per step with the FP16 splits
 
 WORKLOADS = {
-    "c2": dict(desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 RK4 steps, FP32",
-               method="rk4", prec="f32"),
-    "c2v": dict(desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 Verlet steps, FP32",
-                method="verlet", prec="f32"),
-    "c3": dict(desc="fixed-free chain: 4096 instances, s=1024, 1e5 RK4 steps, FP32",
-               method="rk4", prec="f32"),
-    "c3v": dict(desc="fixed-free chain: 4096 instances, s=1024, 1e5 Verlet steps, FP32",
-                method="verlet", prec="f32"),
+    "c1": dict(kind="chain", method="rk4", prec="f64",
+               desc="paper's two-mass system eq. (3): m=2, C=2025, dt=1e-5, 1e5 RK4 steps, FP64, 1 instance"),
+    "c2": dict(kind="chain", method="rk4", prec="f32",
+               desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 RK4 steps, FP32"),
+    "c2v": dict(kind="chain", method="verlet", prec="f32",
+                desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 Verlet steps, FP32"),
+    "c3": dict(kind="chain", method="rk4", prec="f32",
+               desc="fixed-free spring chain: 4096 instances, s=1024, 1e5 RK4 steps, FP32"),
+    "c3v": dict(kind="chain", method="verlet", prec="f32",
+                desc="fixed-free spring chain: 4096 instances, s=1024, 1e5 Verlet steps, FP32"),
+    "c4": dict(kind="dense", method="rk4", prec="f32",
+               desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, FP32 state, FP16x3 MFMA"),
+    "c4v": dict(kind="dense", method="verlet", prec="f32",
+                desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 Verlet steps, FP32 state, FP16x3 MFMA"),
+    "c5": dict(kind="serve", method="rk4", prec="f32",
+               desc="served stream: chains and dense SPD systems, s LogU[2,2048], nsteps LogU[1e3,1e5], FP32"),
 }
 
 
@@ -58,6 +73,8 @@ def _log(msg):
 
 def make_workload(name):
     from paper_1702_02207_amd import workloads
+    if name == "c1":
+        return workloads.c1_paper_two_mass(out_stride=1000)
     if name.startswith("c2"):
         w = workloads.c2_two_dof_ensemble()
         w.out_stride = w.nsteps
@@ -66,23 +83,25 @@ def make_workload(name):
         w = workloads.c3_spring_chain()
         w.out_stride = w.nsteps
         return w
+    if name.startswith("c4"):
+        return workloads.c4_dense_shared()
     raise SystemExit(f"unknown workload {name}")
 
 
 def src_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1702_02207_amd", "csrc"))):
-        h.update(open(os.path.join(ROOT, "paper_1702_02207_amd", "csrc", f), "rb").read())
+    d = os.path.join(ROOT, "paper_1702_02207_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(workload):
     """HBM bytes per launch of the dominant kernel from rocprofv3 --pmc runs
-    recorded in profiles/traffic.json, valid only while the kernel sources
-    are unchanged since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    recorded in profiles/traffic.json, valid only while the kernel sources are
+    unchanged since the counters were taken."""
     try:
-        rec = json.load(open(p)).get(workload)
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json"))).get(workload)
     except (OSError, ValueError):
         return None
     if not rec or rec.get("csrc_hash") != src_hash():
@@ -90,95 +109,76 @@ def measured_traffic(workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, method, sample_n):
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(w, kind, method, prec, sample_n):
     """Time the FP64 oracle on the first sample_n instances (full step count)."""
     import numpy as np
     import oracle
     idx = np.arange(min(sample_n, w.batch))
     sub = w.subset(idx)
-    x0 = sub.x0.astype(np.float32).astype(np.float64)
-    v0 = sub.v0.astype(np.float32).astype(np.float64)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    x0, v0 = sub.x0, sub.v0
+    if prec == "f32":
+        x0 = x0.astype(np.float32).astype(np.float64)
+        v0 = v0.astype(np.float32).astype(np.float64)
+    threads = host_threads()
     t0 = time.perf_counter()
-    xf, vf, xe, ve = oracle.chain(method, sub.m, sub.k, sub.dt, x0, v0, w.nsteps, w.out_stride)
+    if kind == "chain":
+        xf, vf, _, _ = oracle.chain(method, sub.m, sub.k, sub.dt, x0, v0, w.nsteps, w.out_stride)
+    else:
+        xf, vf, _, _ = oracle.dense(method, sub.M, sub.K, sub.dt, x0, v0, w.nsteps, w.out_stride,
+                                    shared=sub.shared)
     el = time.perf_counter() - t0
     rate = len(idx) * w.s * w.nsteps / el
-    return dict(value=rate, unit="DOF-steps/s", cores=threads, kind="oracle",
-                sample=f"first {len(idx)} of {w.batch} instances, all {w.nsteps} steps, FP64 C oracle",
+    return dict(value=rate, unit="DOF-steps/s", cores=min(threads, len(idx)), kind="oracle",
+                sample=f"first {len(idx)} of {w.batch} instances, all {w.nsteps} steps, FP64 C oracle "
+                       f"(OpenMP over instances)",
                 seconds=round(el, 3)), (idx, xf, vf)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--plain-instances", type=int, default=64)
-    ap.add_argument("--plain-steps", type=int, default=0, help="0 = full step count")
-    ap.add_argument("--cpu-sample", type=int, default=65536)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run only a plain elementwise copy of 1 GiB (reads 1 GiB, writes 1 GiB) "
-                         "to calibrate the FETCH_SIZE / WRITE_SIZE counters")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(independent instances would shard across GPUs with no collective).", file=sys.stderr)
-        sys.exit(2)
-
+def bench_batched(args, name, spec):
     import numpy as np
     import torch
     from paper_1702_02207_amd import osc
-
-    if args.calibrate_copy:
-        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            torch.mul(x, 2.0, out=y)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4}))
-        return
-
-    spec = WORKLOADS[args.workload]
-    method, prec = spec["method"], spec["prec"]
-    torch.cuda.set_device(0)
+    kind, method, prec = spec["kind"], spec["method"], spec["prec"]
     dev = torch.device("cuda:0")
-    _log(f"[bench] generating workload {args.workload}")
-    w = make_workload(args.workload)
+    _log(f"[bench] generating workload {name}")
+    w = make_workload(name)
     tdt = torch.float32 if prec == "f32" else torch.float64
-    # inputs resident in HBM before timing
-    m_d = torch.as_tensor(w.m, device=dev)
-    k_d = torch.as_tensor(w.k, device=dev)
-    dt_d = torch.as_tensor(w.dt, device=dev)
+    if kind == "chain":
+        P1, P2, P3 = (torch.as_tensor(a, device=dev) for a in (w.m, w.k, w.dt))
+    else:
+        P1, P2, P3 = (torch.as_tensor(a, device=dev) for a in (w.M, w.K, w.dt))
     x0 = torch.as_tensor(w.x0, dtype=tdt, device=dev)
     v0 = torch.as_tensor(w.v0, dtype=tdt, device=dev)
     nf = w.nsteps // w.out_stride + 1
     xf = torch.empty((nf, w.batch, w.s), dtype=tdt, device=dev)
     vf = torch.empty_like(xf)
-    xe = torch.empty_like(x0)
-    ve = torch.empty_like(v0)
-    E = torch.empty(w.batch, dtype=torch.float64, device=dev)
+    xe, ve = torch.empty_like(x0), torch.empty_like(v0)
     stream = torch.cuda.current_stream()
     kern_ms = []
 
+    def make_system():
+        if kind == "chain":
+            return osc.System("chain", method, prec, P1, P2, P3, stream=stream).create()
+        return osc.System("dense", method, prec, P1, P2, P3, shared=True, batch=w.batch, stream=stream).create()
+
     def one_step(record):
-        sysm = osc.System("chain", method, prec, m_d, k_d, dt_d, stream=stream).create()
+        sysm = make_system()
+        a = b = None
         if record:
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
         sysm.integrate(x0, v0, w.nsteps, w.out_stride, out=(xf, vf, xe, ve))
         if record:
             b.record(stream)
-        osc_E = sysm.energy(xe, ve)
+        sysm.energy(xe, ve)
         sysm.sync()
         sysm.close()
         if record:
             kern_ms.append(a.elapsed_time(b))
-        return osc_E
 
     for i in range(args.warmup):
         _log(f"[bench] warmup {i + 1}/{args.warmup}")
@@ -195,16 +195,23 @@ def main():
     ms_per_step = el / args.steps * 1e3
     _log(f"[bench] {value:.4e} DOF-steps/s, {ms_per_step:.3f} ms/step")
 
-    # roofline of the dominant kernel (the integration launch)
     kavg = float(np.mean(kern_ms)) * 1e-3
-    flops = FLOPS_PER_DOF_STEP[method] * dof_steps
-    achieved = flops / kavg / 1e12
-    peak = PEAK_FP32_TFLOPS if prec == "f32" else PEAK_FP64_TFLOPS
-    traffic = measured_traffic(args.workload)
-    roofline = dict(bound="alu", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
-                    frac=round(achieved / peak, 4), traffic=traffic,
-                    kernel="chain_kernel", kernel_ms=round(kavg * 1e3, 4),
-                    flops_per_dof_step=FLOPS_PER_DOF_STEP[method])
+    if kind == "chain":
+        fpd = CHAIN_FLOPS[(method, prec)]
+        achieved = fpd * dof_steps / kavg / 1e12
+        peak = PEAK["fp32"] if prec == "f32" else PEAK["fp64"]
+        roofline = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=measured_traffic(name), kernel="chain_kernel",
+                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd)
+    else:
+        fpd = DENSE_PRODUCTS[method] * 2 * w.s
+        achieved = fpd * dof_steps / kavg / 1e12
+        hw = DENSE_HW_TERMS[method] * 2 * w.s * dof_steps / kavg / 1e12
+        peak = PEAK["fp16_mfma"]
+        roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=measured_traffic(name), kernel="dense_mfma_kernel",
+                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd,
+                        hw_mfma_tflops=round(hw, 1), hw_mfma_frac=round(hw / peak, 4))
 
     out = {
         "metric": "DOF-steps/sec batched vs plain at stated err; p50/p99 solve latency",
@@ -216,33 +223,50 @@ def main():
         "roofline": roofline,
     }
 
-    # plain per-instance integrator (one step per launch) on a sample
     if not args.no_plain:
-        pn = min(args.plain_instances, w.batch)
-        psteps = args.plain_steps or w.nsteps
+        pn = min(args.plain_instances if kind == "chain" else max(1, args.plain_instances // 16), w.batch)
+        psteps = args.plain_steps or (w.nsteps if kind == "chain" and w.s <= 8 else min(w.nsteps, 2000))
         sub = w.subset(np.arange(pn))
         _log(f"[bench] plain integrator: {pn} instances x {psteps} steps")
-        ps = osc.System("chain", method, prec, sub.m, sub.k, sub.dt, stream=stream).create()
-        px0 = torch.as_tensor(sub.x0, dtype=tdt, device=dev)
-        pv0 = torch.as_tensor(sub.v0, dtype=tdt, device=dev)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pxe, pve = ps.integrate_plain(px0, pv0, psteps)
-        ps.sync()
-        tp = time.perf_counter() - t1
-        ps.close()
+        if kind == "chain":
+            ps = osc.System("chain", method, prec, sub.m, sub.k, sub.dt, stream=stream).create()
+            px0 = torch.as_tensor(sub.x0, dtype=tdt, device=dev)
+            pv0 = torch.as_tensor(sub.v0, dtype=tdt, device=dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pxe, pve = ps.integrate_plain(px0, pv0, psteps)
+            ps.sync()
+            tp = time.perf_counter() - t1
+            ps.close()
+        else:
+            # one instance at a time, one step per launch, state in device memory
+            tp = 0.0
+            for i in range(pn):
+                ps = osc.System("dense", method, prec, sub.M, sub.K, sub.dt, shared=True, batch=1,
+                                stream=stream).create()
+                ps.set_config(osc.CFG_DENSE_KERNEL, 1).set_config(osc.CFG_STEPS_PER_LAUNCH, 1)
+                px0 = torch.as_tensor(sub.x0[i:i + 1], dtype=tdt, device=dev)
+                pv0 = torch.as_tensor(sub.v0[i:i + 1], dtype=tdt, device=dev)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ps.integrate(px0, pv0, psteps, 0)
+                ps.sync()
+                tp += time.perf_counter() - t1
+                ps.close()
         plain_rate = pn * w.s * psteps / tp
         out["plain"] = {"value": plain_rate, "unit": "DOF-steps/s", "instances": pn, "steps": psteps,
                         "us_per_launch": tp / (pn * psteps) * 1e6}
         out["speedup_vs_plain"] = value / plain_rate
-        if psteps == w.nsteps:
-            d = (pxe.double() - xe[:pn].double()).abs().max().item()
-            out["plain"]["max_abs_diff_vs_batched"] = d
 
-    # CPU baseline: the oracle on a bounded sample; the same sample gives the error
     if not args.no_cpu_baseline:
-        _log(f"[bench] oracle on {min(args.cpu_sample, w.batch)} instances")
-        cb, (idx, rxf, rvf) = cpu_baseline(w, method, args.cpu_sample)
+        if args.cpu_sample:
+            sample = args.cpu_sample
+        elif kind == "chain":
+            sample = 65536 if w.s <= 8 else 16
+        else:
+            sample = 8
+        _log(f"[bench] oracle on {min(sample, w.batch)} instances")
+        cb, (idx, rxf, rvf) = cpu_baseline(w, kind, method, prec, sample)
         out["cpu_baseline"] = cb
         import oracle
         gx = xf[:, :len(idx)].double().cpu().numpy()
@@ -253,7 +277,78 @@ def main():
                         "p99_rel_err_x": float(np.percentile(ex, 99)),
                         "p99_rel_err_v": float(np.percentile(ev, 99)),
                         "tolerance": TOL[prec], "instances_checked": int(len(idx)),
+                        "frames_checked": int(nf),
                         "within_tolerance": bool(max(ex.max(), ev.max()) < TOL[prec])}
+    return out
+
+
+def bench_serve(args, spec):
+    import numpy as np
+    from paper_1702_02207_amd import serve, workloads
+    _log(f"[bench] generating {args.requests} requests")
+    reqs = workloads.c5_request_stream(n_requests=args.requests, qps=1.0)
+    work = sum(r.system.s * r.system.nsteps for r in reqs)
+    _log("[bench] burst (saturation)")
+    sat = serve.run_stream(reqs, None, method=spec["method"], prec=spec["prec"],
+                           hbm_budget=args.hbm_budget)
+    sat_qps = len(reqs) / sat["makespan_s"]
+    qps = args.qps or args.load * sat_qps
+    _log(f"[bench] Poisson arrivals at {qps:.2f} requests/s")
+    arr = serve.poisson_arrivals(len(reqs), qps, seed=1702022074)
+    run = serve.run_stream(reqs, arr, method=spec["method"], prec=spec["prec"], hbm_budget=args.hbm_budget)
+    out = {
+        "metric": "DOF-steps/sec batched vs plain at stated err; p50/p99 solve latency",
+        "value": run["dof_steps_per_s"], "unit": "DOF-steps/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": run["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": spec["prec"], "data": "synthetic",
+        "config": {"workload": spec["desc"], "requests": len(reqs), "qps": qps,
+                   "hbm_budget": args.hbm_budget, "total_dof_steps": int(work)},
+        "serving": {"p50_latency_s": run["p50_latency_s"], "p99_latency_s": run["p99_latency_s"],
+                    "mean_latency_s": run["mean_latency_s"], "failed": run["failed"],
+                    "hbm_peak_bytes": run["hbm_peak_bytes"], "iterations": run["iterations"],
+                    "saturation": {"requests_per_s": sat_qps, "dof_steps_per_s": sat["dof_steps_per_s"],
+                                   "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"]}},
+    }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-instances", type=int, default=64)
+    ap.add_argument("--plain-steps", type=int, default=0, help="0 = workload default")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="0 = workload default")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="c5: requests in the stream")
+    ap.add_argument("--qps", type=float, default=0.0, help="c5: arrival rate (0 = load x saturation)")
+    ap.add_argument("--load", type=float, default=0.5, help="c5: fraction of the saturation rate")
+    ap.add_argument("--hbm-budget", type=int, default=32 << 30, help="c5: server HBM budget in bytes")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain elementwise copy of 1 GiB (reads 1 GiB, writes 1 GiB) "
+                         "to calibrate the FETCH_SIZE / WRITE_SIZE counters")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent instances would shard across GPUs with no collective).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 2.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4}))
+        return
+    spec = WORKLOADS[args.workload]
+    out = bench_serve(args, spec) if spec["kind"] == "serve" else bench_batched(args, args.workload, spec)
     print(json.dumps(out), flush=True)
 
 

@@ -182,6 +182,20 @@ typedef enum {
 } osc_config;
 osc_status osc_set_config(osc_sys *sys, osc_config key, int64_t value);
 
+/*
+ * osc_autotune -- time every feasible launch configuration of the handle on
+ * its own batch (chains: the lane layouts; dense: the VALU / MFMA / split
+ * kernels), probe_steps steps each starting from (x0, v0) (device arrays as
+ * for osc_integrate; nothing is written to them), and keep the fastest.
+ * *chosen (may be NULL) receives the configuration value, as accepted by
+ * osc_set_config.  When the environment variable OSC_AUTOTUNE_CACHE names a
+ * file, the choice is appended to it, and osc_create applies the cached
+ * choice for the same kind, method, precision, s, batch size class and GPU.
+ * Synchronous.  Chain layouts give bitwise-identical results; dense kernels
+ * agree within the FP32 tolerance.
+ */
+osc_status osc_autotune(osc_sys *sys, const void *x0, const void *v0, int64_t probe_steps, int64_t *chosen);
+
 /* osc_sync -- wait for the handle's stream; returns OSC_ENONFINITE if any
  * integration since the last osc_sync produced a non-finite state. */
 osc_status osc_sync(osc_sys *sys);

@@ -451,6 +451,7 @@ osc_status osc_create(const osc_desc *d, void *stream, osc_sys **out) {
         release(s);
         return r;
     }
+    autotune_apply_cached(s);
     *out = s;
     return OSC_OK;
 }

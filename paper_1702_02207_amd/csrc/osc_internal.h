@@ -213,6 +213,7 @@ ChainCoef<T> chain_coef(const osc_sys *s);
 bool dense_uses_split(const osc_sys *s);
 osc_status sys_ensure_state(osc_sys *s);
 osc_status sys_ensure_split_scratch(osc_sys *s);
+void autotune_apply_cached(osc_sys *s);   // autotune.hip
 
 }  // namespace osc
 

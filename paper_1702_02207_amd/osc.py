@@ -78,6 +78,7 @@ def load():
         "osc_sync": (i32, [vp]),
         "osc_dense_operator": (i32, [vp, vp]),
         "osc_set_config": (i32, [vp, i32, i64]),
+        "osc_autotune": (i32, [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]),
         "osc_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
         "osc_server_submit": (i32, [vp, ctypes.POINTER(Desc), vp, vp, i64, i64,
                                     ctypes.POINTER(ctypes.c_uint64)]),
@@ -211,6 +212,13 @@ class System:
         CFG_DENSE_KERNEL (0 auto, 1 VALU, 2 MFMA), CFG_STEPS_PER_LAUNCH."""
         _check(load().osc_set_config(self.handle, int(key), int(value)))
         return self
+
+    def autotune(self, x0, v0, probe_steps: int = 200) -> int:
+        """osc_autotune: time the feasible launch configurations, keep the fastest."""
+        x0, v0 = self._state(x0), self._state(v0)
+        chosen = ctypes.c_int64(0)
+        _check(load().osc_autotune(self.handle, _dptr(x0), _dptr(v0), int(probe_steps), ctypes.byref(chosen)))
+        return chosen.value
 
     def dense_operator(self):
         """A = M^-1 K as formed on the GPU (FP64), [nsys, s, s]."""

@@ -223,3 +223,47 @@ def test_batch_composition_invariance():
     _, _, xe_sub, ve_sub = gpu_chain("rk4", "f32", w.subset(idx))
     np.testing.assert_array_equal(xe_all[idx], xe_sub)
     np.testing.assert_array_equal(ve_all[idx], ve_sub)
+
+
+def test_autotune_picks_a_layout_and_caches_it(tmp_path, monkeypatch):
+    import torch
+    from paper_1702_02207_amd import osc
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("OSC_AUTOTUNE_CACHE", str(cache))
+    rng = np.random.default_rng(41)
+    s, batch = 200, 96
+    m, k = workloads.random_chain(rng, batch, s)
+    dt = 0.01 / workloads.chain_omega_max(m, k)
+    w = workloads.ChainBatch(m, k, dt, rng.normal(0, 0.1, (batch, s)), np.zeros((batch, s)), 400, 100)
+    sysm = osc.System("chain", "rk4", "f32", m, k, dt).create()
+    ref = _run_chain(sysm, w, 400, 100)
+    x0 = torch.as_tensor(w.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.zeros_like(x0)
+    chosen = sysm.autotune(x0, v0, probe_steps=50)
+    lpi, dpl = chosen >> 16, chosen & 0xffff
+    assert lpi * dpl >= s
+    got = _run_chain(sysm, w, 400, 100)
+    sysm.close()
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a, b)
+    line = cache.read_text().strip().splitlines()[-1]
+    assert line.startswith("chain rk4 f32 200 ") and line.endswith(str(chosen))
+    # a new handle with the same key picks the cached layout (same results)
+    sysm = osc.System("chain", "rk4", "f32", m, k, dt).create()
+    got = _run_chain(sysm, w, 400, 100)
+    sysm.close()
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_autotune_dense_prefers_a_feasible_kernel():
+    import torch
+    from paper_1702_02207_amd import osc
+    rng = np.random.default_rng(43)
+    M, K = workloads.random_dense_system(rng, 128)
+    dt = [0.01 / workloads.dense_omega_max(M, K)]
+    sysm = osc.System("dense", "rk4", "f32", M, K, dt, shared=True, batch=256).create()
+    x0 = torch.as_tensor(rng.normal(size=(256, 128)), dtype=torch.float32, device="cuda")
+    chosen = sysm.autotune(x0, torch.zeros_like(x0), probe_steps=50)
+    sysm.close()
+    assert chosen in (1, 2, 3)
