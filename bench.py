@@ -306,6 +306,7 @@ def bench_serve(args, spec):
         "serving": {"p50_latency_s": run["p50_latency_s"], "p99_latency_s": run["p99_latency_s"],
                     "mean_latency_s": run["mean_latency_s"], "failed": run["failed"],
                     "hbm_peak_bytes": run["hbm_peak_bytes"], "iterations": run["iterations"],
+                    "worker_setup_s": run["worker_setup_s"], "worker_iterate_s": run["worker_iterate_s"],
                     "saturation": {"requests_per_s": sat_qps, "dof_steps_per_s": sat["dof_steps_per_s"],
                                    "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"]}},
     }

@@ -247,6 +247,8 @@ typedef struct osc_server_counters {
     int64_t submitted, completed, failed, queued, active;
     int64_t iterations;
     size_t hbm_in_use, hbm_peak;   /* accounted device bytes of admitted requests */
+    double setup_s;                /* worker time spent admitting (allocation, operator formation) */
+    double iterate_s;              /* worker time spent in scheduler iterations (launch to sync) */
 } osc_server_counters;
 
 /* osc_server_create -- start a server (and its worker thread) on the current

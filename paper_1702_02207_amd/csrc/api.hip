@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI declared in include/osc.h.
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -35,7 +36,10 @@ void release(osc_sys *s) {
     for (void *p : {(void *)s->m, (void *)s->k, (void *)s->h, s->coef, (void *)s->flag, s->plain_state,
                     (void *)s->A, s->Bh, s->Bl, s->F1, s->F2, s->state, s->split_scratch})
         pool_free(p);
+    pool_free(s->mfma_items);
     if (s->split_graph) (void)hipGraphExecDestroy(s->split_graph);
+    delete[] s->inv_betas;
+    delete[] s->h_host;
     delete s;
 }
 
@@ -251,20 +255,29 @@ osc_status create_dense(osc_sys *s, const osc_desc *d) {
     }
     s->theta_max = worst;
     s->h_shared = hh[0];
-    if (std::is_same<T, float>::value && s->shared && dense_mfma_pad(n) > 0) {
-        // FP16 operator fragments of B^ = beta h^2 A with ||B^||_inf in [1/2, 1)
-        const double rowsum = th[0] * th[0];
-        int e = 0;
-        (void)std::frexp(rowsum > 0.0 ? rowsum : 1.0, &e);
-        const double beta = std::ldexp(1.0, -e);
-        s->inv_beta = (float)std::ldexp(1.0, e);
+    s->h_host = new (std::nothrow) double[nsys];
+    if (!s->h_host) return fail(OSC_ENOMEM, "host allocation failed");
+    for (int64_t i = 0; i < nsys; ++i) s->h_host[i] = hh[i];
+    if (std::is_same<T, float>::value && dense_mfma_pad(n) > 0) {
+        // FP16 operator fragments of B^ = beta h^2 A with ||B^||_inf in [1/2, 1), per system
         const size_t fe = dense_mfma_fragment_elems(n);
-        s->F1 = pool_alloc(fe * sizeof(_Float16));
-        s->F2 = pool_alloc(fe * sizeof(_Float16));
-        if (!s->F1 || !s->F2) return fail(OSC_ENOMEM, "device memory exhausted for MFMA operator fragments");
-        if ((r = dense_mfma_fragments(n, s->A, beta * hh[0] * hh[0], static_cast<_Float16 *>(s->F1),
-                                      static_cast<_Float16 *>(s->F2), st)))
-            return r;
+        s->F1 = pool_alloc(nsys * fe * sizeof(_Float16));
+        s->F2 = pool_alloc(nsys * fe * sizeof(_Float16));
+        s->inv_betas = new (std::nothrow) float[nsys];
+        if (!s->F1 || !s->F2 || !s->inv_betas)
+            return fail(OSC_ENOMEM, "memory exhausted for MFMA operator fragments");
+        for (int64_t i = 0; i < nsys; ++i) {
+            const double rowsum = th[i] * th[i];
+            int e = 0;
+            (void)std::frexp(rowsum > 0.0 ? rowsum : 1.0, &e);
+            const double beta = std::ldexp(1.0, -e);
+            s->inv_betas[i] = (float)std::ldexp(1.0, e);
+            if ((r = dense_mfma_fragments(n, s->A + i * ss, beta * hh[i] * hh[i],
+                                          static_cast<_Float16 *>(s->F1) + i * fe,
+                                          static_cast<_Float16 *>(s->F2) + i * fe, st)))
+                return r;
+        }
+        s->inv_beta = s->inv_betas[0];
         OSC_HIP(hipStreamSynchronize(st));
     }
     return OSC_OK;
@@ -329,6 +342,59 @@ osc_status integrate_split(osc_sys *s, const void *x0, const void *v0, int64_t n
     return dense_split_run<T>(a, s->method, s->stream, &s->split_graph, &s->split_graph_len, gsteps);
 }
 
+// Per-instance operators on the matrix cores: one work-list item (one
+// workgroup) per instance, each with its own fragments and scale; chunked
+// state is kept per instance ([batch][4][s] plus one scale each).
+osc_status integrate_mfma_items(osc_sys *s, const DenseMfmaLaunch &base, int64_t nsteps) {
+    const int64_t B = s->batch, n = s->s;
+    const size_t fe = dense_mfma_fragment_elems((int)n);
+    const int64_t chunk = s->steps_per_launch > 0 ? s->steps_per_launch : (nsteps > 0 ? nsteps : 1);
+    const bool chunked = nsteps > chunk;
+    osc_status r;
+    if (chunked && (r = ensure_state(s))) return r;
+    const size_t bytes = B * sizeof(DenseMfmaItem);
+    if (s->mfma_items_bytes < bytes) {
+        pool_free(s->mfma_items);
+        s->mfma_items = pool_alloc(bytes);
+        s->mfma_items_bytes = s->mfma_items ? bytes : 0;
+        if (!s->mfma_items) return fail(OSC_ENOMEM, "device memory exhausted for the MFMA work list");
+    }
+    std::vector<DenseMfmaItem> items(B);
+    float *st = static_cast<float *>(s->state);
+    for (int64_t n0 = 0; n0 < nsteps || n0 == 0; n0 += chunk) {
+        const int64_t cnt = std::min(chunk, nsteps - n0);
+        for (int64_t b = 0; b < B; ++b) {
+            DenseMfmaLaunch a = base;
+            a.batch = 1;
+            a.B1 = static_cast<const _Float16 *>(s->F1) + b * fe;
+            a.B2 = static_cast<const _Float16 *>(s->F2) + b * fe;
+            a.inv_beta = s->inv_betas[b];
+            a.h = s->h_host[b];
+            a.x0 = base.x0 + b * n;
+            a.v0 = base.v0 + b * n;
+            a.xf = base.xf ? base.xf + b * n : nullptr;
+            a.vf = base.vf ? base.vf + b * n : nullptr;
+            a.xe = base.xe ? base.xe + b * n : nullptr;
+            a.ve = base.ve ? base.ve + b * n : nullptr;
+            a.n0 = n0;
+            a.nsteps = cnt;
+            a.load_mode = n0 == 0 ? LOAD_USER : LOAD_STATE;
+            a.store_mode = n0 + cnt == nsteps ? STORE_USER : STORE_STATE;
+            a.state = chunked ? st + b * 4 * n : nullptr;
+            a.sigma = chunked ? st + 4 * B * n + b : nullptr;
+            items[b].L = a;
+        }
+        OSC_HIP(hipMemcpyAsync(s->mfma_items, items.data(), bytes, hipMemcpyHostToDevice, s->stream));
+        if ((r = dense_mfma_launch_items(static_cast<const DenseMfmaItem *>(s->mfma_items), B,
+                                         dense_mfma_pad((int)n), s->method, s->stream)))
+            return r;
+        // the host vector is reused for the next chunk: the copy must have been consumed
+        if (n0 + chunk < nsteps) OSC_HIP(hipStreamSynchronize(s->stream));
+        if (nsteps == 0) break;
+    }
+    return OSC_OK;
+}
+
 template <typename T>
 osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
                            void *xf, void *vf, void *xe, void *ve) {
@@ -345,13 +411,16 @@ osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t n
             a.x0 = static_cast<const float *>(x0);
             a.v0 = static_cast<const float *>(v0);
             a.out_stride = out_stride;
+            a.frame_plane = s->batch * (int64_t)s->s;
             a.xf = static_cast<float *>(xf);
             a.vf = static_cast<float *>(vf);
             a.xe = static_cast<float *>(xe);
             a.ve = static_cast<float *>(ve);
             a.nonfinite = s->flag;
-            return run_chunks(s, a, nsteps,
-                              [&](const DenseMfmaLaunch &c) { return dense_mfma_launch(c, s->method, s->stream); });
+            if (s->shared)
+                return run_chunks(s, a, nsteps,
+                                  [&](const DenseMfmaLaunch &c) { return dense_mfma_launch(c, s->method, s->stream); });
+            return integrate_mfma_items(s, a, nsteps);
         }
     }
     DenseLaunch<T> a{};

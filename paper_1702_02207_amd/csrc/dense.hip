@@ -149,7 +149,7 @@ __global__ void dense_prepare_kernel(int s, const double *__restrict__ A, size_t
         Bh[o] = (T)b;
         if constexpr (std::is_same<T, float>::value) Bl[o] = (T)(b - (double)Bh[o]);
     }
-    atomic_max_pos(theta_bound, sqrt(rowsum));
+    atomic_max_pos(theta_bound + sys, sqrt(rowsum));
 }
 
 // Power iteration for lambda_max of A^T (same spectrum as A), one workgroup;

@@ -46,8 +46,9 @@ __device__ __forceinline__ f4 mfma(half8 a, half8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
+// One workgroup's share of launch a: the 16 instances of column tile `tile`.
 template <int RT, int NW, int METHOD>
-__global__ void __launch_bounds__(64 * NW, 1) dense_mfma_kernel(DenseMfmaLaunch a) {
+__device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t tile) {
     constexpr int kNW = NW;          // waves per workgroup
     constexpr int SP = 16 * RT * NW; // padded dimension
     constexpr int KS = SP / 32;      // k-steps of 32
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(64 * NW, 1) dense_mfma_kernel(DenseMfmaLaunch 
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, quad = lane >> 4;
-    const int64_t b = (int64_t)blockIdx.x * kNC + col;
+    const int64_t b = tile * kNC + col;
     const bool active = b < a.batch;
     const int s = a.s;
     const int row0 = wave * 16 * RT;
@@ -238,7 +239,7 @@ __global__ void __launch_bounds__(64 * NW, 1) dense_mfma_kernel(DenseMfmaLaunch 
     };
     const bool untouched = a.load_mode == LOAD_USER;
     auto write_frame = [&](int64_t f, bool initial) {
-        const size_t fo = (size_t)f * plane;
+        const size_t fo = (size_t)f * a.frame_plane;
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -353,6 +354,19 @@ __global__ void __launch_bounds__(64 * NW, 1) dense_mfma_kernel(DenseMfmaLaunch 
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
 }
 
+template <int RT, int NW, int METHOD>
+__global__ void __launch_bounds__(64 * NW, 1) dense_mfma_kernel(DenseMfmaLaunch a) {
+    mfma_run<RT, NW, METHOD>(a, blockIdx.x);
+}
+
+// Work list: workgroup i runs items[i] (a launch of at most 16 instances with
+// its own operator, e.g. one served request).
+template <int RT, int NW, int METHOD>
+__global__ void __launch_bounds__(64 * NW, 1) dense_mfma_items_kernel(const DenseMfmaItem *__restrict__ items) {
+    const DenseMfmaLaunch a = items[blockIdx.x].L;
+    mfma_run<RT, NW, METHOD>(a, 0);
+}
+
 // Operator fragments: for row tile T, k-step q, lane l, element j:
 // row = 16 T + l % 16, k = 32 q + 8 (l / 16) + j.
 __global__ void dense_mfma_fragments_kernel(int s, int sp, const double *__restrict__ A, double scale,
@@ -381,7 +395,31 @@ void launch_rt(const DenseMfmaLaunch &a, int method, hipStream_t st) {
         hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_VERLET>), dim3(blocks), dim3(64 * NW), 0, st, a);
 }
 
+template <int RT, int NW>
+void launch_items_rt(const DenseMfmaItem *items, int64_t n, int method, hipStream_t st) {
+    if (method == OSC_RK4)
+        hipLaunchKernelGGL((dense_mfma_items_kernel<RT, NW, OSC_RK4>), dim3((unsigned)n), dim3(64 * NW), 0, st, items);
+    else
+        hipLaunchKernelGGL((dense_mfma_items_kernel<RT, NW, OSC_VERLET>), dim3((unsigned)n), dim3(64 * NW), 0, st,
+                           items);
+}
+
 }  // namespace
+
+osc_status dense_mfma_launch_items(const DenseMfmaItem *items, int64_t nitems, int pad, int method,
+                                   hipStream_t st) {
+    if (nitems == 0) return OSC_OK;
+    if (nitems > 0x7fffffff) return fail(OSC_EINVAL, "work list too long for one launch");
+    switch (pad / 64) {
+        case 1: launch_items_rt<2, 2>(items, nitems, method, st); break;
+        case 2: launch_items_rt<2, 4>(items, nitems, method, st); break;
+        case 3: launch_items_rt<2, 6>(items, nitems, method, st); break;
+        case 4: launch_items_rt<2, 8>(items, nitems, method, st); break;
+        default: return fail(OSC_ENOTSUP, "MFMA path needs s <= 256");
+    }
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
 
 int dense_mfma_pad(int s) { return s <= 256 ? ((s + 63) / 64) * 64 : 0; }
 

@@ -3,10 +3,10 @@
 // One workgroup cannot hold an s = 2048 operator (16 MB in FP32), and one
 // workgroup streaming it would take hundreds of microseconds per step.  Here a
 // time step is two kernels: rows are spread over workgroups (64 rows each) and
-// the k dimension of every product over the workgroup's 4 wavefronts, which
-// reduce their partial sums through LDS.  The kernel boundary is the global
-// synchronisation point between the products of a step, so no workgroup ever
-// waits for another.  A device-side step counter lets the same two launches
+// the k dimension of every product over the workgroup's 16 wavefronts, which
+// reduce their partial sums through LDS in a fixed order (results are
+// reproducible).  The kernel boundary is the global synchronisation point
+// between the products of a step, so no workgroup ever waits for another.  A device-side step counter lets the same two launches
 // be replayed (hipGraph) for every step.
 //
 // RK4 (exact linear Taylor form): phase 1 forms P = B x (split coefficients)
@@ -24,7 +24,8 @@ namespace osc {
 namespace {
 
 constexpr int kRows = 64;     // rows per workgroup (one per lane)
-constexpr int kWaves = 4;     // k-split
+constexpr int kWaves = 16;    // k-split: 16 wavefronts each take 1/16 of the columns
+constexpr int kThreads = 64 * kWaves;
 
 template <typename T>
 __device__ __forceinline__ T fmat(T a, T b, T c) {
@@ -45,7 +46,7 @@ __device__ __forceinline__ void comp_add(T &hi, T &lo, T y) {
 }
 
 // Partial products of the rows [r0, r0 + 64) over this wave's k-range,
-// reduced across the 4 waves.  Returns (for lane = row) up to three sums:
+// reduced across the wavefronts.  Returns (for lane = row) up to three sums:
 // y1 = Bh u1 (+ Bl u1 when lo), y2 = Bh u2.
 template <typename T, bool LO, bool TWO>
 __device__ __forceinline__ void rows_product(const DenseSplitLaunch<T> &a, const T *Bh, const T *Bl, const T *u1,
@@ -55,18 +56,33 @@ __device__ __forceinline__ void rows_product(const DenseSplitLaunch<T> &a, const
     const int row = r0 + lane;
     const int kper = (s + kWaves - 1) / kWaves;
     const int k0 = wave * kper, k1 = min(s, k0 + kper);
-    T a1 = T(0), a1l = T(0), a2 = T(0);
+    // four independent partial sums per product keep several loads in flight
+    T a1[4] = {T(0), T(0), T(0), T(0)}, a1l[4] = {T(0), T(0), T(0), T(0)}, a2[4] = {T(0), T(0), T(0), T(0)};
     if (row < s) {
-        for (int j = k0; j < k1; ++j) {
+        int j = k0;
+        for (; j + 4 <= k1; j += 4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const T bh = Bh[(size_t)(j + q) * s + row];
+                const T v1 = u1[j + q];
+                a1[q] = fmat(bh, v1, a1[q]);
+                if constexpr (LO) a1l[q] = fmat(Bl[(size_t)(j + q) * s + row], v1, a1l[q]);
+                if constexpr (TWO) a2[q] = fmat(bh, u2[j + q], a2[q]);
+            }
+        }
+        for (; j < k1; ++j) {
             const T bh = Bh[(size_t)j * s + row];
             const T v1 = u1[j];
-            a1 = fmat(bh, v1, a1);
-            if constexpr (LO) a1l = fmat(Bl[(size_t)j * s + row], v1, a1l);
-            if constexpr (TWO) a2 = fmat(bh, u2[j], a2);
+            a1[0] = fmat(bh, v1, a1[0]);
+            if constexpr (LO) a1l[0] = fmat(Bl[(size_t)j * s + row], v1, a1l[0]);
+            if constexpr (TWO) a2[0] = fmat(bh, u2[j], a2[0]);
         }
     }
-    red[0][wave][lane] = a1 + a1l;
-    if constexpr (TWO) red[1][wave][lane] = a2;
+    const T s1 = (a1[0] + a1[1]) + (a1[2] + a1[3]);
+    const T s1l = (a1l[0] + a1l[1]) + (a1l[2] + a1l[3]);
+    const T s2 = (a2[0] + a2[1]) + (a2[2] + a2[3]);
+    red[0][wave][lane] = s1 + s1l;
+    if constexpr (TWO) red[1][wave][lane] = s2;
     __syncthreads();
     y1 = T(0);
     y2 = T(0);
@@ -77,9 +93,9 @@ __device__ __forceinline__ void rows_product(const DenseSplitLaunch<T> &a, const
     }
 }
 
-// grid: (row blocks, instances); 256 threads; only wave 0 writes results.
+// grid: (row blocks, instances); kThreads threads; only wave 0 writes results.
 template <typename T, int METHOD>
-__global__ void __launch_bounds__(256) split_phase1(DenseSplitLaunch<T> a) {
+__global__ void __launch_bounds__(kThreads) split_phase1(DenseSplitLaunch<T> a) {
     __shared__ T red[2][kWaves][kRows];
     const int64_t b = blockIdx.y;
     const int s = a.s;
@@ -116,7 +132,7 @@ __global__ void __launch_bounds__(256) split_phase1(DenseSplitLaunch<T> a) {
 }
 
 template <typename T, int METHOD>
-__global__ void __launch_bounds__(256) split_phase2(DenseSplitLaunch<T> a) {
+__global__ void __launch_bounds__(kThreads) split_phase2(DenseSplitLaunch<T> a) {
     __shared__ T red[2][kWaves][kRows];
     const int64_t b = blockIdx.y;
     const int s = a.s;
@@ -172,7 +188,7 @@ __global__ void __launch_bounds__(256) split_phase2(DenseSplitLaunch<T> a) {
 // State from the caller's (x0, v0), frame 0, the step counter, and for Verlet
 // the carried P_0 = B x_0.
 template <typename T, int METHOD>
-__global__ void __launch_bounds__(256) split_load(DenseSplitLaunch<T> a) {
+__global__ void __launch_bounds__(kThreads) split_load(DenseSplitLaunch<T> a) {
     __shared__ T red[2][kWaves][kRows];
     const int64_t b = blockIdx.y;
     const int s = a.s;
@@ -229,7 +245,8 @@ template <typename T, int METHOD>
 osc_status split_run_m(const DenseSplitLaunch<T> &a, hipStream_t st, hipGraphExec_t *graph, int64_t *graph_steps,
                        int64_t graph_chunk) {
     const dim3 grid((a.s + kRows - 1) / kRows, (unsigned)a.batch);
-    if (a.load_mode == LOAD_USER) hipLaunchKernelGGL((split_load<T, METHOD>), grid, dim3(256), 0, st, a);
+    const dim3 block(kThreads);
+    if (a.load_mode == LOAD_USER) hipLaunchKernelGGL((split_load<T, METHOD>), grid, block, 0, st, a);
     OSC_HIP(hipGetLastError());
     int64_t left = a.nsteps;
     // replay a captured chunk of steps while whole chunks remain
@@ -240,8 +257,8 @@ osc_status split_run_m(const DenseSplitLaunch<T> &a, hipStream_t st, hipGraphExe
             hipGraph_t g = nullptr;
             OSC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             for (int64_t k = 0; k < graph_chunk; ++k) {
-                hipLaunchKernelGGL((split_phase1<T, METHOD>), grid, dim3(256), 0, st, a);
-                hipLaunchKernelGGL((split_phase2<T, METHOD>), grid, dim3(256), 0, st, a);
+                hipLaunchKernelGGL((split_phase1<T, METHOD>), grid, block, 0, st, a);
+                hipLaunchKernelGGL((split_phase2<T, METHOD>), grid, block, 0, st, a);
             }
             OSC_HIP(hipStreamEndCapture(st, &g));
             hipError_t e = hipGraphInstantiate(graph, g, nullptr, nullptr, 0);
@@ -255,8 +272,8 @@ osc_status split_run_m(const DenseSplitLaunch<T> &a, hipStream_t st, hipGraphExe
         }
     }
     for (; left > 0; --left) {
-        hipLaunchKernelGGL((split_phase1<T, METHOD>), grid, dim3(256), 0, st, a);
-        hipLaunchKernelGGL((split_phase2<T, METHOD>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((split_phase1<T, METHOD>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((split_phase2<T, METHOD>), grid, block, 0, st, a);
     }
     OSC_HIP(hipGetLastError());
     if (a.store_mode & STORE_USER) {

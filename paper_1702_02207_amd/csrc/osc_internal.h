@@ -198,10 +198,16 @@ struct DenseMfmaLaunch {
     float *state;
     float *sigma;              // [batch] per-instance scale, carried with the state
     int64_t nsteps, n0, out_stride;
+    int64_t frame_plane;       // elements between consecutive frames (normally batch * s)
     float *xf, *vf, *xe, *ve;
     int *nonfinite;
     int load_mode, store_mode;
 };
+struct DenseMfmaItem {
+    DenseMfmaLaunch L;         // batch <= 16: one workgroup
+};
+// Work list of MFMA launches that all pad to `pad` (dense_mfma_pad).
+osc_status dense_mfma_launch_items(const DenseMfmaItem *items, int64_t nitems, int pad, int method, hipStream_t st);
 int dense_mfma_pad(int s);                       // padded size (multiple of 64), 0 if s > 256
 size_t dense_mfma_fragment_elems(int s);         // FP16 elements per operator part
 osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *B1, _Float16 *B2, hipStream_t st);
@@ -234,8 +240,12 @@ struct osc_sys {
     double *A = nullptr;                 // dense: A = M^-1 K [nsys][s][s] (FP64)
     void *Bh = nullptr, *Bl = nullptr;   // dense: h^2 A column-major, hi / lo parts
     int64_t nsys = 0;                    // dense: number of distinct systems
-    void *F1 = nullptr, *F2 = nullptr;   // dense shared FP32: MFMA operator fragments
+    void *F1 = nullptr, *F2 = nullptr;   // dense FP32, s <= 256: MFMA operator fragments [nsys]
     float inv_beta = 1.0f;
+    float *inv_betas = nullptr;          // host copy, one per system
+    double *h_host = nullptr;            // host copy of each system's step
+    void *mfma_items = nullptr;          // device work list (per-instance operators)
+    size_t mfma_items_bytes = 0;
     double h_shared = 0.0;
     // configuration (osc_set_config)
     int dense_kernel = 0;                // 0 auto, 1 VALU, 2 MFMA, 3 split

@@ -25,6 +25,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "osc_internal.h"
@@ -54,7 +55,7 @@ struct Req {
     // device side (worker thread only)
     osc_sys *sys = nullptr;
     void *dx0 = nullptr, *dv0 = nullptr, *dxf = nullptr, *dvf = nullptr, *dxe = nullptr, *dve = nullptr;
-    bool split = false;
+    bool split = false, mfma = false;
     int64_t done = 0, chunk = 0;
     // results
     std::vector<unsigned char> hxf, hvf, hxe, hve;
@@ -95,8 +96,9 @@ int64_t estimate_bytes(const osc_desc &d, int64_t nframes) {
 double step_seconds(const Req &r) {
     const double s = r.desc.s;
     if (r.desc.kind == OSC_CHAIN) return 2e-7 + 4e-9 * s;
-    if (r.split) return 1.5e-5 + 1e-12 * s * s;
-    return 1e-6 + 2e-10 * s * s;
+    if (r.split) return 2.0e-5 + 8e-12 * s * s;
+    if (r.mfma) return 1e-6 + 2e-11 * s * s;
+    return 2e-6 + 1.2e-9 * s * s;
 }
 
 struct Server {
@@ -111,6 +113,7 @@ struct Server {
     bool stopping = false;
     size_t in_use = 0, peak = 0;
     int64_t submitted = 0, completed = 0, failed = 0, iterations = 0;
+    double setup_s = 0.0, iterate_s = 0.0;
     std::thread worker;
     hipStream_t streams[kStreams] = {};
     void *stage = nullptr;       // pinned host staging of work lists
@@ -177,6 +180,7 @@ void Server::setup(Req *r) {
         r->dvf = pool_alloc(r->nframes * s * r->elem);
     }
     r->split = r->desc.kind == OSC_DENSE && dense_uses_split(r->sys);
+    r->mfma = r->desc.kind == OSC_DENSE && r->desc.prec == OSC_F32 && r->sys->F1 != nullptr;
     st = sys_ensure_state(r->sys);
     if (st == OSC_OK && r->split) st = sys_ensure_split_scratch(r->sys);
     if (st != OSC_OK || !r->dx0 || !r->dv0 || !r->dxe || !r->dve || (r->nframes > 0 && (!r->dxf || !r->dvf))) {
@@ -199,6 +203,7 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
     std::map<std::pair<int, int64_t>, std::vector<ChainItem<T>>> chains;   // (method, layout)
     std::map<std::pair<int, int>, std::vector<DenseItem<T>>> denses;       // (method, smax bucket)
     std::map<std::pair<int, int>, int> dense_smax;
+    std::map<std::pair<int, int>, std::vector<DenseMfmaItem>> mfmas;       // (method, padded s)
     const size_t want_elem = sizeof(T);
     int next_stream = 0;
     for (size_t i = 0; i < act.size(); ++i) {
@@ -229,6 +234,32 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
             it.b = 0;
             const int64_t key = ((int64_t)sy->cfg.lpi << 16) | sy->cfg.dpl;
             chains[{(int)sy->method, key}].push_back(it);
+        } else if (std::is_same<T, float>::value && sy->F1) {
+            // matrix cores, one workgroup per request (operator resident in registers)
+            DenseMfmaItem it{};
+            DenseMfmaLaunch &a = it.L;
+            a.batch = 1;
+            a.s = sy->s;
+            a.B1 = sy->F1;
+            a.B2 = sy->F2;
+            a.inv_beta = sy->inv_beta;
+            a.h = sy->h_shared;
+            a.x0 = static_cast<const float *>(r->dx0);
+            a.v0 = static_cast<const float *>(r->dv0);
+            a.state = static_cast<float *>(sy->state);
+            a.sigma = static_cast<float *>(sy->state) + 4 * (size_t)sy->s;
+            a.nsteps = c;
+            a.n0 = n0;
+            a.out_stride = r->out_stride;
+            a.frame_plane = sy->s;
+            a.xf = static_cast<float *>(r->dxf);
+            a.vf = static_cast<float *>(r->dvf);
+            a.xe = static_cast<float *>(r->dxe);
+            a.ve = static_cast<float *>(r->dve);
+            a.nonfinite = sy->flag;
+            a.load_mode = load;
+            a.store_mode = store;
+            mfmas[{(int)sy->method, dense_mfma_pad(sy->s)}].push_back(it);
         } else if (!r->split) {
             DenseItem<T> it{};
             it.L.batch = 1;
@@ -289,6 +320,7 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
     size_t bytes = 0;
     for (auto &g : chains) bytes += (g.second.size() * sizeof(ChainItem<T>) + 255) / 256 * 256;
     for (auto &g : denses) bytes += (g.second.size() * sizeof(DenseItem<T>) + 255) / 256 * 256;
+    for (auto &g : mfmas) bytes += (g.second.size() * sizeof(DenseMfmaItem) + 255) / 256 * 256;
     if (bytes == 0) return;
     if (bytes > stage_bytes) {
         if (stage) (void)hipHostFree(stage);
@@ -315,6 +347,11 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
         spans.push_back({off, g.second.size()});
         off += (g.second.size() * sizeof(DenseItem<T>) + 255) / 256 * 256;
     }
+    for (auto &g : mfmas) {
+        std::memcpy(static_cast<char *>(stage) + off, g.second.data(), g.second.size() * sizeof(DenseMfmaItem));
+        spans.push_back({off, g.second.size()});
+        off += (g.second.size() * sizeof(DenseMfmaItem) + 255) / 256 * 256;
+    }
     hipEvent_t ready;
     (void)hipEventCreateWithFlags(&ready, hipEventDisableTiming);
     (void)hipMemcpyAsync(items, stage, off, hipMemcpyHostToDevice, streams[0]);
@@ -335,6 +372,15 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
         (void)hipStreamWaitEvent(st, ready, 0);
         (void)dense_launch_items<T>(reinterpret_cast<const DenseItem<T> *>(static_cast<char *>(items) + spans[k].first),
                                     (int64_t)spans[k].second, dense_smax[g.first], g.first.first, st);
+        ++k;
+    }
+    for (auto &g : mfmas) {
+        hipStream_t st = streams[next_stream];
+        next_stream = (next_stream + 1) % kStreams;
+        (void)hipStreamWaitEvent(st, ready, 0);
+        (void)dense_mfma_launch_items(
+            reinterpret_cast<const DenseMfmaItem *>(static_cast<char *>(items) + spans[k].first),
+            (int64_t)spans[k].second, g.first.second, g.first.first, st);
         ++k;
     }
     (void)hipEventDestroy(ready);
@@ -415,12 +461,20 @@ void Server::loop() {
                 continue;
             }
         }
+        const double t0 = now_s();
         for (Req *r : admitted) setup(r);
+        const double t1 = now_s();
         {
             std::lock_guard<std::mutex> lk(mu);
             act = active;
         }
         if (!act.empty()) run_iteration(act);
+        const double t2 = now_s();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            setup_s += t1 - t0;
+            iterate_s += t2 - t1;
+        }
     }
 }
 
@@ -557,6 +611,8 @@ osc_status osc_server_stats(osc_server *srv, osc_server_counters *out) {
     out->iterations = S.iterations;
     out->hbm_in_use = S.in_use;
     out->hbm_peak = S.peak;
+    out->setup_s = S.setup_s;
+    out->iterate_s = S.iterate_s;
     return OSC_OK;
 }
 

@@ -54,7 +54,8 @@ class RequestInfo(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("active", ctypes.c_int64), ("iterations", ctypes.c_int64),
-                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t)]
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("setup_s", ctypes.c_double), ("iterate_s", ctypes.c_double)]
 
 
 _lib = None

@@ -69,5 +69,6 @@ def run_stream(reqs, arrivals: Optional[np.ndarray] = None, method: str = "rk4",
         "makespan_s": makespan, "dof_steps": int(work), "dof_steps_per_s": work / makespan,
         "offered_qps": (len(reqs) / arrivals[-1]) if arrivals is not None and len(arrivals) else None,
         "hbm_peak_bytes": int(stats["hbm_peak"]), "iterations": int(stats["iterations"]),
+        "worker_setup_s": stats["setup_s"], "worker_iterate_s": stats["iterate_s"],
         "results": results,
     }

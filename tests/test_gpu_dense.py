@@ -208,3 +208,14 @@ def test_dense_split_graph_replays_match_eager(method):
         for a, b in zip(ref, got):
             np.testing.assert_array_equal(a, b)
     sysm.close()
+
+
+def test_per_instance_stability_check_covers_every_system():
+    """An unstable step on any one of several per-instance systems is rejected."""
+    from paper_1702_02207_amd import osc
+    M = np.stack([np.eye(3)] * 3)
+    K = np.stack([np.diag([1.0, 4.0, 9.0])] * 3)
+    dt = np.array([0.01, 0.01, 5.0])          # h omega = 15 for the last system
+    with pytest.raises(osc.OscError) as e:
+        osc.System("dense", "rk4", "f32", M, K, dt, shared=False).create()
+    assert e.value.status == osc.OSC_EUNSTABLE
