@@ -1,10 +1,11 @@
 // Continuous-batching server for single-instance integration requests.
 //
-// A worker thread owns every device resource of the admitted requests.  Each
-// scheduler iteration it
+// A worker thread owns the scheduling.  Each scheduler iteration it
 //   1. admits queued requests first come first served while the accounted
-//      device bytes stay within the HBM budget and a slot is free
-//      (allocation, parameter upload and operator formation happen here);
+//      device bytes stay within the HBM budget and a slot is free; a setup
+//      thread then allocates, uploads and forms the operator on a stream of
+//      its own, concurrently with the running iterations, and hands the
+//      request to the worker when it is ready;
 //   2. advances every admitted request by one chunk of time steps: chains and
 //      small dense systems go into work-list launches, one per kernel shape,
 //      spread over four streams; large dense systems run their split path
@@ -106,23 +107,28 @@ struct Server {
     int device = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_setup;
     std::deque<Req *> queue;
-    std::vector<Req *> active;
+    std::deque<Req *> preparing;   // admitted, waiting for or in setup
+    std::vector<Req *> active;     // ready: part of every iteration
     std::map<uint64_t, Req *> all;
     std::atomic<uint64_t> next_ticket{1};
     bool stopping = false;
     size_t in_use = 0, peak = 0;
     int64_t submitted = 0, completed = 0, failed = 0, iterations = 0;
     double setup_s = 0.0, iterate_s = 0.0;
-    std::thread worker;
+    std::thread worker, setup_worker;
     hipStream_t streams[kStreams] = {};
+    hipStream_t setup_stream = nullptr;
+    int64_t in_setup = 0;
     void *stage = nullptr;       // pinned host staging of work lists
     size_t stage_bytes = 0;
     void *items = nullptr;       // device copy of work lists
     size_t items_bytes = 0;
 
     void loop();
-    void setup(Req *r);
+    void setup_loop();
+    bool setup(Req *r);   // false: the request has been finished (failed) and may be gone
     void run_iteration(std::vector<Req *> &act);
     void finish(Req *r, osc_status st, const std::string &msg);
     void release_device(Req *r);
@@ -151,7 +157,7 @@ void Server::finish(Req *r, osc_status st, const std::string &msg) {
     cv_done.notify_all();
 }
 
-void Server::setup(Req *r) {
+bool Server::setup(Req *r) {
     const size_t s = (size_t)r->desc.s;
     r->hxe.assign(s * r->elem, 0);
     r->hve.assign(s * r->elem, 0);
@@ -159,17 +165,17 @@ void Server::setup(Req *r) {
     r->hvf.assign(r->nframes * s * r->elem, 0);
     if (cfg.fake_executor) {
         r->chunk = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(*r)));
-        return;
+        return true;
     }
     osc_desc d = r->desc;
     d.M = r->M.data();
     d.K = r->K.data();
     d.dt = r->dt.data();
     d.param_mem = OSC_MEM_HOST;
-    osc_status st = osc_create(&d, streams[0], &r->sys);
+    osc_status st = osc_create(&d, setup_stream, &r->sys);
     if (st != OSC_OK) {
         finish(r, st, osc_last_error());
-        return;
+        return false;
     }
     r->dx0 = pool_alloc(s * r->elem);
     r->dv0 = pool_alloc(s * r->elem);
@@ -185,16 +191,21 @@ void Server::setup(Req *r) {
     if (st == OSC_OK && r->split) st = sys_ensure_split_scratch(r->sys);
     if (st != OSC_OK || !r->dx0 || !r->dv0 || !r->dxe || !r->dve || (r->nframes > 0 && (!r->dxf || !r->dvf))) {
         finish(r, OSC_ENOMEM, "device memory exhausted while admitting a request");
-        return;
+        return false;
     }
-    if (hipMemcpyAsync(r->dx0, r->x0.data(), s * r->elem, hipMemcpyHostToDevice, streams[0]) != hipSuccess ||
-        hipMemcpyAsync(r->dv0, r->v0.data(), s * r->elem, hipMemcpyHostToDevice, streams[0]) != hipSuccess ||
-        hipStreamSynchronize(streams[0]) != hipSuccess) {
+    if (hipMemcpyAsync(r->dx0, r->x0.data(), s * r->elem, hipMemcpyHostToDevice, setup_stream) != hipSuccess ||
+        hipMemcpyAsync(r->dv0, r->v0.data(), s * r->elem, hipMemcpyHostToDevice, setup_stream) != hipSuccess ||
+        hipStreamSynchronize(setup_stream) != hipSuccess) {
         finish(r, OSC_EDEVICE, "upload of the initial state failed");
-        return;
+        return false;
     }
     r->chunk = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(*r)));
     if (r->split) r->chunk = std::max<int64_t>(64, r->chunk / 64 * 64);   // whole captured graphs
+    // the setup stream is drained; from here on the handle's own stream is
+    // one the worker drains every iteration, so the completion path never
+    // waits behind another request's setup
+    r->sys->stream = streams[0];
+    return true;
 }
 
 // Build, upload and launch the work lists of one precision.
@@ -438,13 +449,40 @@ void Server::run_iteration(std::vector<Req *> &act) {
     }
 }
 
+void Server::setup_loop() {
+    if (!cfg.fake_executor) (void)hipSetDevice(device);
+    for (;;) {
+        Req *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_setup.wait(lk, [&] { return stopping || !preparing.empty(); });
+            if (preparing.empty()) {
+                if (stopping) break;
+                continue;
+            }
+            r = preparing.front();
+            preparing.pop_front();
+            ++in_setup;
+        }
+        const double t0 = now_s();
+        const bool ok = setup(r);   // a failed request is finished there; r must not be touched after
+        const double t1 = now_s();
+        std::lock_guard<std::mutex> lk(mu);
+        --in_setup;
+        setup_s += t1 - t0;
+        if (ok) active.push_back(r);
+        cv_work.notify_all();
+    }
+}
+
 void Server::loop() {
     if (!cfg.fake_executor) (void)hipSetDevice(device);
     for (;;) {
-        std::vector<Req *> admitted, act;
+        std::vector<Req *> act;
         {
             std::unique_lock<std::mutex> lk(mu);
-            while (!queue.empty() && (int)active.size() < cfg.max_slots) {
+            bool admitted = false;
+            while (!queue.empty() && (int64_t)(active.size() + preparing.size()) + in_setup < cfg.max_slots) {
                 Req *r = queue.front();
                 if (cfg.hbm_budget && in_use + (size_t)r->bytes > cfg.hbm_budget) break;   // wait for memory
                 queue.pop_front();
@@ -452,29 +490,22 @@ void Server::loop() {
                 peak = std::max(peak, in_use);
                 r->st = RState::ACTIVE;
                 r->t_admit = now_s();
-                active.push_back(r);
-                admitted.push_back(r);
+                preparing.push_back(r);
+                admitted = true;
             }
-            if (admitted.empty() && active.empty()) {
-                if (stopping) break;
+            if (admitted) cv_setup.notify_all();
+            if (active.empty()) {
+                if (stopping && queue.empty() && preparing.empty() && in_setup == 0) break;
                 cv_work.wait_for(lk, std::chrono::milliseconds(20));
                 continue;
             }
-        }
-        const double t0 = now_s();
-        for (Req *r : admitted) setup(r);
-        const double t1 = now_s();
-        {
-            std::lock_guard<std::mutex> lk(mu);
             act = active;
         }
-        if (!act.empty()) run_iteration(act);
+        const double t1 = now_s();
+        run_iteration(act);
         const double t2 = now_s();
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            setup_s += t1 - t0;
-            iterate_s += t2 - t1;
-        }
+        std::lock_guard<std::mutex> lk(mu);
+        iterate_s += t2 - t1;
     }
 }
 
@@ -505,15 +536,17 @@ osc_status osc_server_create(const osc_server_config *cfg, osc_server **out) {
             delete srv;
             return fail(OSC_EDEVICE, "no HIP device");
         }
-        for (auto &st : S.streams) {
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-                for (auto &t : S.streams)
-                    if (t) (void)hipStreamDestroy(t);
-                delete srv;
-                return fail(OSC_EDEVICE, "stream creation failed");
-            }
+        bool ok = hipStreamCreateWithFlags(&S.setup_stream, hipStreamNonBlocking) == hipSuccess;
+        for (auto &st : S.streams) ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (!ok) {
+            for (auto &t : S.streams)
+                if (t) (void)hipStreamDestroy(t);
+            if (S.setup_stream) (void)hipStreamDestroy(S.setup_stream);
+            delete srv;
+            return fail(OSC_EDEVICE, "stream creation failed");
         }
     }
+    S.setup_worker = std::thread([&S] { S.setup_loop(); });
     S.worker = std::thread([&S] { S.loop(); });
     *out = srv;
     return OSC_OK;
@@ -607,7 +640,7 @@ osc_status osc_server_stats(osc_server *srv, osc_server_counters *out) {
     out->completed = S.completed;
     out->failed = S.failed;
     out->queued = (int64_t)S.queue.size();
-    out->active = (int64_t)S.active.size();
+    out->active = (int64_t)(S.active.size() + S.preparing.size()) + S.in_setup;
     out->iterations = S.iterations;
     out->hbm_in_use = S.in_use;
     out->hbm_peak = S.peak;
@@ -631,15 +664,22 @@ void osc_server_destroy(osc_server *srv) {
         }
         S.queue.clear();
         S.cv_work.notify_all();
+        S.cv_setup.notify_all();
         S.cv_done.notify_all();
     }
     if (S.worker.joinable()) S.worker.join();
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.cv_setup.notify_all();
+    }
+    if (S.setup_worker.joinable()) S.setup_worker.join();
     for (auto &kv : S.all) delete kv.second;
     S.all.clear();
     if (S.stage) (void)hipHostFree(S.stage);
     pool_free(S.items);
     for (auto &st : S.streams)
         if (st) (void)hipStreamDestroy(st);
+    if (S.setup_stream) (void)hipStreamDestroy(S.setup_stream);
     delete srv;
 }
 
