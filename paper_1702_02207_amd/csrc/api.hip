@@ -205,13 +205,13 @@ osc_status create_dense(osc_sys *s, const osc_desc *d) {
     s->Bh = pool_alloc(nsys * ss * sizeof(T));
     s->Bl = std::is_same<T, float>::value ? pool_alloc(nsys * ss * sizeof(T)) : nullptr;
     s->flag = static_cast<int *>(pool_alloc(64));
-    DevBuf Lc, Y, scratch, theta;
+    DevBuf Lc, Inv, scratch, theta;
     Lc.p = pool_alloc(mbytes);
-    Y.p = pool_alloc(mbytes);
+    Inv.p = pool_alloc(nsys * dense_form_scratch_elems(n) * sizeof(double));
     scratch.p = pool_alloc(64);
     theta.p = pool_alloc(nsys * sizeof(double));
     if (!s->m || !s->k || !s->A || !s->h || !s->Bh || (std::is_same<T, float>::value && !s->Bl) || !s->flag ||
-        !Lc.p || !Y.p || !scratch.p || !theta.p)
+        !Lc.p || !Inv.p || !scratch.p || !theta.p)
         return fail(OSC_ENOMEM, "device memory / HBM budget exhausted in osc_create");
     osc_status r;
     if ((r = copy_in(s->m, d->M, mbytes, d->param_mem, st))) return r;
@@ -222,7 +222,7 @@ osc_status create_dense(osc_sys *s, const osc_desc *d) {
     OSC_HIP(hipMemsetAsync(theta.p, 0, nsys * sizeof(double), st));
     int *notspd = static_cast<int *>(scratch.p);
     int *bad = notspd + 1;
-    if ((r = dense_form_a(n, nsys, s->m, s->k, static_cast<double *>(Lc.p), static_cast<double *>(Y.p), s->A,
+    if ((r = dense_form_a(n, nsys, s->m, s->k, static_cast<double *>(Lc.p), static_cast<double *>(Inv.p), s->A,
                           notspd, st)))
         return r;
     if ((r = dense_prepare<T>(n, nsys, s->A, s->h, static_cast<T *>(s->Bh), static_cast<T *>(s->Bl),

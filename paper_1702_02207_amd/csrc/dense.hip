@@ -1,11 +1,8 @@
-// Dense systems of eq. (1): A = M^-1 K formed in FP64 on the GPU, the
-// stability bound, FP64 energy, and a generic (VALU) integrator with one
-// workgroup per instance.
+// Dense systems of eq. (1): the scaled operator, the stability bound, FP64
+// energy, and a generic (VALU) integrator with one workgroup per instance.
+// (A = M^-1 K itself is formed in FP64 by the blocked Cholesky path.)
 //
-// Formation (FP64): M = L L^T by a column-by-column Cholesky factorisation
-// (L kept column-major), Y = L^-1 K by forward substitution and
-// A = L^-T Y by back substitution, each right-hand-side column on its own
-// lane.  Scaled operator for the integrators: B = h^2 A, stored
+// Scaled operator for the integrators: B = h^2 A, stored
 // column-major (Bc[j*s + i] = B_ij) so that the lanes of a wave, which own
 // consecutive rows, read consecutive addresses.  FP32 keeps B as hi + lo.
 //
@@ -52,104 +49,64 @@ __device__ double block_sum(double v, double *scratch) {
     return t;
 }
 
-// ------------------------------------------------------------------ Cholesky
-// One workgroup per system (blockIdx.x = system); M row-major, lower triangle read.
-constexpr int kCholThreads = 1024;
-
-__global__ void __launch_bounds__(kCholThreads) cholesky_kernel(int s, const double *__restrict__ M, size_t mstride,
-                                                                double *__restrict__ Lc, size_t lstride, int *status) {
-    __shared__ double scratch[kCholThreads / 64];
-    __shared__ double sdiag;
-    M += blockIdx.x * mstride;
-    Lc += blockIdx.x * lstride;
-    for (int j = 0; j < s; ++j) {
-        double part = 0.0;
-        for (int p = threadIdx.x; p < j; p += kCholThreads) {
-            const double l = Lc[(size_t)p * s + j];
-            part += l * l;
-        }
-        part = block_sum<kCholThreads>(part, scratch);
-        if (threadIdx.x == 0) {
-            const double d = M[(size_t)j * s + j] - part;
-            sdiag = (d > 0.0 && __builtin_isfinite(d)) ? sqrt(d) : -1.0;
-            if (sdiag > 0.0) Lc[(size_t)j * s + j] = sdiag;
-        }
-        __syncthreads();
-        const double ljj = sdiag;
-        if (!(ljj > 0.0)) {
-            if (threadIdx.x == 0) atomicOr(status, 1);
-            return;   // uniform: every thread read the same sdiag
-        }
-        for (int i = j + 1 + threadIdx.x; i < s; i += kCholThreads) {
-            double acc = M[(size_t)i * s + j];
-            for (int p = 0; p < j; ++p) acc -= Lc[(size_t)p * s + i] * Lc[(size_t)p * s + j];
-            Lc[(size_t)j * s + i] = acc / ljj;
-        }
-        __syncthreads();
-    }
-}
-
-// Y = L^-1 K (forward substitution), one column of K per lane; blockIdx.y = system.
-__global__ void __launch_bounds__(64) forward_kernel(int s, const double *__restrict__ Lc, size_t lstride,
-                                                     const double *__restrict__ K, size_t kstride,
-                                                     double *__restrict__ Y, size_t ystride) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    Lc += blockIdx.y * lstride;
-    K += blockIdx.y * kstride;
-    Y += blockIdx.y * ystride;
-    if (c >= s) return;
-    for (int i = 0; i < s; ++i) {
-        double acc = K[(size_t)i * s + c];
-        for (int p = 0; p < i; ++p) acc -= Lc[(size_t)p * s + i] * Y[(size_t)p * s + c];
-        Y[(size_t)i * s + c] = acc / Lc[(size_t)i * s + i];
-    }
-}
-
-// A = L^-T Y (back substitution), row-major A; blockIdx.y = system.
-__global__ void __launch_bounds__(64) backward_kernel(int s, const double *__restrict__ Lc, size_t lstride,
-                                                      const double *__restrict__ Y, size_t ystride,
-                                                      double *__restrict__ A, size_t astride) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    Lc += blockIdx.y * lstride;
-    Y += blockIdx.y * ystride;
-    A += blockIdx.y * astride;
-    if (c >= s) return;
-    for (int i = s - 1; i >= 0; --i) {
-        double acc = Y[(size_t)i * s + c];
-        for (int p = i + 1; p < s; ++p) acc -= Lc[(size_t)i * s + p] * A[(size_t)p * s + c];
-        A[(size_t)i * s + c] = acc / Lc[(size_t)i * s + i];
-    }
-}
-
 __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
     atomicMax(reinterpret_cast<unsigned long long *>(addr), __double_as_longlong(v));
 }
 
-// Scaled operator B = h^2 A, column-major, and the row-sum bound
-// theta^2 <= max_i h^2 sum_j |A_ij| (every eigenvalue is bounded by any induced norm).
+// Scaled operator B = h^2 A, column-major (FP32: hi + lo), one 64x64 tile per
+// workgroup, transposed through LDS so that both the row-major read of A and
+// the column-major write of B are coalesced.
 template <typename T>
-__global__ void dense_prepare_kernel(int s, const double *__restrict__ A, size_t astride,
-                                     const double *__restrict__ dt, T *Bh, T *Bl, size_t bstride,
-                                     double *theta_bound, int *bad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // row
-    const int sys = blockIdx.y;
-    if (i >= s) return;
-    A += sys * astride;
+__global__ void __launch_bounds__(256) dense_prepare_kernel(int s, const double *__restrict__ A, size_t astride,
+                                                            const double *__restrict__ dt, T *Bh, T *Bl,
+                                                            size_t bstride, int tiles, int *bad) {
+    __shared__ double t[64][65];
+    const int64_t sys = blockIdx.x / ((int64_t)tiles * tiles);
+    const int tile = (int)(blockIdx.x % ((int64_t)tiles * tiles));
+    const int i0 = (tile / tiles) * 64, j0 = (tile % tiles) * 64;
     const double h = dt[sys];
-    if (!(h > 0.0) || !__builtin_isfinite(h)) {
-        atomicOr(bad, 1);
-        return;
+    A += sys * astride;
+    bool fine = h > 0.0 && __builtin_isfinite(h);
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+        const int i = idx / 64, j = idx % 64;
+        double b = 0.0;
+        if (i0 + i < s && j0 + j < s) {
+            b = h * h * A[(size_t)(i0 + i) * s + j0 + j];
+            fine = fine && __builtin_isfinite(b);
+        }
+        t[i][j] = b;
     }
-    double rowsum = 0.0;
-    for (int j = 0; j < s; ++j) {
-        const double b = h * h * A[(size_t)i * s + j];
-        if (!__builtin_isfinite(b)) atomicOr(bad, 1);
-        rowsum += fabs(b);
-        const size_t o = sys * bstride + (size_t)j * s + i;
-        Bh[o] = (T)b;
-        if constexpr (std::is_same<T, float>::value) Bl[o] = (T)(b - (double)Bh[o]);
+    if (!fine) atomicOr(bad, 1);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+        const int j = idx / 64, i = idx % 64;
+        if (i0 + i < s && j0 + j < s) {
+            const double b = t[i][j];
+            const size_t o = sys * bstride + (size_t)(j0 + j) * s + i0 + i;
+            Bh[o] = (T)b;
+            if constexpr (std::is_same<T, float>::value) Bl[o] = (T)(b - (double)Bh[o]);
+        }
     }
-    atomic_max_pos(theta_bound + sys, sqrt(rowsum));
+}
+
+// Row-sum bound theta^2 <= max_i h^2 sum_j |A_ij| (every eigenvalue is
+// bounded by any induced norm): one wave per row, each lane summing a fixed
+// strided subset in order, then a fixed butterfly, so the bound is the same
+// on every run.
+__global__ void __launch_bounds__(256) dense_rowsum_kernel(int s, int64_t nsys, const double *__restrict__ A,
+                                                           size_t astride, const double *__restrict__ dt,
+                                                           double *theta_bound) {
+    const int lane = threadIdx.x % 64;
+    const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int64_t sys = row / s;
+    const int i = (int)(row % s);
+    if (sys >= nsys) return;   // whole waves only: the row index is wave-uniform
+    const double h = dt[sys];
+    const double *a = A + sys * astride + (size_t)i * s;
+    double acc = 0.0;
+    for (int j = lane; j < s; j += 64) acc += fabs(h * h * a[j]);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) atomic_max_pos(theta_bound + sys, sqrt(acc));
 }
 
 // Power iteration for lambda_max of A^T (same spectrum as A), one workgroup;
@@ -477,27 +434,21 @@ template osc_status dense_launch_items<double>(const DenseItem<double> *, int64_
 
 // ------------------------------------------------------------- host helpers
 
-osc_status dense_form_a(int s, int64_t nsys, const double *M, const double *K, double *Lc, double *Y, double *A,
-                        int *status, hipStream_t st) {
-    if (nsys == 0) return OSC_OK;
-    const size_t ss = (size_t)s * s;
-    hipLaunchKernelGGL(cholesky_kernel, dim3((unsigned)nsys), dim3(kCholThreads), 0, st, s, M, ss, Lc, ss, status);
-    OSC_HIP(hipGetLastError());
-    const dim3 g((s + 63) / 64, (unsigned)nsys);
-    hipLaunchKernelGGL(forward_kernel, g, dim3(64), 0, st, s, Lc, ss, K, ss, Y, ss);
-    OSC_HIP(hipGetLastError());
-    hipLaunchKernelGGL(backward_kernel, g, dim3(64), 0, st, s, Lc, ss, Y, ss, A, ss);
-    OSC_HIP(hipGetLastError());
-    return OSC_OK;
-}
-
 template <typename T>
 osc_status dense_prepare(int s, int64_t nsys, const double *A, const double *dt, T *Bh, T *Bl, double *theta,
                          int *bad, hipStream_t st) {
     if (nsys == 0) return OSC_OK;
     const size_t ss = (size_t)s * s;
-    const dim3 g((s + 255) / 256, (unsigned)nsys);
-    hipLaunchKernelGGL((dense_prepare_kernel<T>), g, dim3(256), 0, st, s, A, ss, dt, Bh, Bl, ss, theta, bad);
+    const int tiles = (s + 63) / 64;
+    const int64_t blocks = nsys * tiles * tiles;
+    const int64_t rows = nsys * s;
+    if (blocks > 0x7fffffff || (rows + 3) / 4 > 0x7fffffff)
+        return fail(OSC_EINVAL, "too many systems for one preparation launch");
+    hipLaunchKernelGGL((dense_prepare_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, s, A, ss, dt, Bh, Bl, ss,
+                       tiles, bad);
+    OSC_HIP(hipGetLastError());
+    hipLaunchKernelGGL(dense_rowsum_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, s, nsys, A, ss, dt,
+                       theta);
     OSC_HIP(hipGetLastError());
     return OSC_OK;
 }

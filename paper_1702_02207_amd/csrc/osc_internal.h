@@ -148,9 +148,11 @@ osc_status dense_launch_items(const DenseItem<T> *items, int64_t nitems, int sma
 // kernel shape bucket of the generic dense integrator for s (0..4)
 int dense_vec_bucket(int s);
 
-// A = M^-1 K for nsys systems ([nsys][s][s] row-major M, K); Lc, Y scratch of
-// the same size; status |= 1 when a Cholesky pivot is not positive.
-osc_status dense_form_a(int s, int64_t nsys, const double *M, const double *K, double *Lc, double *Y, double *A,
+// A = M^-1 K for nsys systems ([nsys][s][s] row-major M, K, A); Lc scratch
+// of the same size, Inv scratch of nsys * dense_form_scratch_elems(s)
+// doubles; status |= 1 when a Cholesky pivot is not positive and finite.
+size_t dense_form_scratch_elems(int s);
+osc_status dense_form_a(int s, int64_t nsys, const double *M, const double *K, double *Lc, double *Inv, double *A,
                         int *status, hipStream_t st);
 // B = h^2 A (column-major, split for FP32) and per-system row-sum bounds
 // theta[sys] >= h omega_max.

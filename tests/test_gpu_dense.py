@@ -32,17 +32,22 @@ def _dense_batch(seed, s, batch, nsteps, stride, shared=True, vscale=0.0):
     return workloads.DenseBatch(M, K, dt, x0, v0, nsteps, stride, shared)
 
 
-def test_operator_matches_oracle_cholesky():
-    import torch
+@pytest.mark.parametrize("s,nsys", [(1, 1), (2, 1), (7, 1), (64, 1), (65, 1), (200, 1), (700, 1),
+                                     (5, 4), (130, 3)])
+def test_operator_matches_oracle_cholesky(s, nsys):
+    """Blocked FP64 formation (64-wide panels: one block, a ragged second
+    block, several blocks) against the oracle's unblocked Cholesky solve."""
     from paper_1702_02207_amd import osc
-    for s in (1, 2, 7, 64, 200):
-        w = _dense_batch(40 + s, s, 2, 10, 0)
-        sysm = osc.System("dense", "rk4", "f64", w.M, w.K, w.dt, shared=True, batch=2).create()
-        A = sysm.dense_operator().cpu().numpy()[0]
-        sysm.sync()
-        sysm.close()
-        ref = oracle.form_a(w.M, w.K)
-        assert np.abs(A - ref).max() <= 1e-12 * np.abs(ref).max()
+    w = _dense_batch(40 + s, s, max(nsys, 2), 10, 0, shared=nsys == 1)
+    sysm = osc.System("dense", "rk4", "f64", w.M, w.K, w.dt, shared=nsys == 1, batch=max(nsys, 2)).create()
+    A = sysm.dense_operator().cpu().numpy()
+    sysm.sync()
+    sysm.close()
+    Ms = w.M.reshape(-1, s, s)
+    Ks = w.K.reshape(-1, s, s)
+    for b in range(Ms.shape[0]):
+        ref = oracle.form_a(Ms[b], Ks[b])
+        assert np.abs(A[b] - ref).max() <= 1e-12 * np.abs(ref).max(), b
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
