@@ -88,10 +88,14 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def src_hash():
+# kernel sources that decide the dominant kernel of each workload family
+TRAFFIC_SOURCES = {"chain": ("chain.hip", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h")}
+
+
+def src_hash(workload):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1702_02207_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in TRAFFIC_SOURCES["dense" if workload.startswith("c4") else "chain"]:
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -104,7 +108,7 @@ def measured_traffic(workload):
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json"))).get(workload)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("csrc_hash") != src_hash():
+    if not rec or rec.get("csrc_hash") != src_hash(workload):
         return None
     return rec.get("bytes_per_launch")
 

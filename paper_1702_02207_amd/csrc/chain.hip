@@ -215,7 +215,7 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
             const int64_t nf = (n / stride + 1) * stride;
             stop = nf < stop ? nf : stop;
         }
-        for (int64_t it = n; it < stop; ++it) {
+        auto step = [&]() {
             if constexpr (METHOD == OSC_RK4) {
                 T Q[DPL];
                 if constexpr (COMP) grp.apply2(x, clh, crh, cll, crl, P);
@@ -248,6 +248,18 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) comp_add(w[j], wl[j], -P[j]);
             }
+        };
+        // 32-bit trip counts keep the loop test on the scalar unit; two
+        // steps per trip halve the loop overhead
+        for (int64_t left = stop - n; left > 0;) {
+            const int cnt = (int)(left < (int64_t(1) << 30) ? left : (int64_t(1) << 30));
+            int k = 0;
+            for (; k + 2 <= cnt; k += 2) {
+                step();
+                step();
+            }
+            if (k < cnt) step();
+            left -= cnt;
         }
         n = stop;
         if (stride > 0 && n % stride == 0) write_frame(n / stride, false);
