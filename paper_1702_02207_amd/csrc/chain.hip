@@ -59,7 +59,10 @@ __device__ __forceinline__ double from_right(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-template <typename T, int DPL, int LPI>
+// FREE: the lane's last DOF is the chain's free end (LPI == 1 and s == DPL),
+// whose right coefficient is exactly zero; its terms are then left out at
+// compile time (same results: a product with +-0 added to a finite value).
+template <typename T, int DPL, int LPI, bool FREE>
 struct Group {
     bool first, last;   // lane is the first / last of its instance's group
 
@@ -88,6 +91,10 @@ struct Group {
         T el = u[0] - prev;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
+            if (FREE && j == DPL - 1) {
+                out[j] = cl[j] * el;
+                continue;
+            }
             const T un = (j + 1 < DPL) ? u[(j + 1 < DPL) ? j + 1 : j] : next;
             const T er = un - u[j];
             out[j] = fmat(cl[j], el, -cr[j] * er);
@@ -104,6 +111,10 @@ struct Group {
         T el = u[0] - prev;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
+            if (FREE && j == DPL - 1) {
+                out[j] = fmat(clh[j], el, cll[j] * el);
+                continue;
+            }
             const T un = (j + 1 < DPL) ? u[(j + 1 < DPL) ? j + 1 : j] : next;
             const T er = un - u[j];
             out[j] = fmat(clh[j], el, fmat(-crh[j], er, fmat(cll[j], el, -crl[j] * er)));
@@ -131,13 +142,14 @@ __device__ __forceinline__ bool finite(T v) { return __builtin_isfinite(v); }
 // One lane of the group that integrates instance b of launch a (sl = lane
 // within the group).  Lanes of an instance outside the batch run on zeros so
 // that their group still answers the DPP exchanges of a full wave.
-template <typename T, int DPL, int LPI, int METHOD>
+template <typename T, int DPL, int LPI, int METHOD, bool FREE = false>
 __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t b, const int sl) {
+    static_assert(!FREE || LPI == 1, "the free end is known at compile time only for one lane per instance");
     constexpr bool COMP = std::is_same<T, float>::value;
     const bool active = b < a.batch;
     const int s = a.s;
     const int d0 = sl * DPL;
-    Group<T, DPL, LPI> grp{sl == 0, sl == LPI - 1};
+    Group<T, DPL, LPI, FREE> grp{sl == 0, sl == LPI - 1};
 
     T clh[DPL], crh[DPL], cll[DPL], crl[DPL];
     T x[DPL], xl[DPL], w[DPL], wl[DPL];
@@ -230,11 +242,17 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
                 for (int j = 0; j < DPL; ++j) {
                     const T pn = (j + 1 < DPL) ? P[(j + 1 < DPL) ? j + 1 : j] : pnext;
                     const T qn = (j + 1 < DPL) ? Q[(j + 1 < DPL) ? j + 1 : j] : qnext;
-                    const T epr = pn - P[j], eqr = qn - Q[j];
-                    const T P2 = fmat(clh[j], epl, -crh[j] * epr);
-                    const T Q2 = fmat(clh[j], eql, -crh[j] * eqr);
-                    epl = epr;
-                    eql = eqr;
+                    T P2, Q2;
+                    if (FREE && j == DPL - 1) {
+                        P2 = clh[j] * epl;
+                        Q2 = clh[j] * eql;
+                    } else {
+                        const T epr = pn - P[j], eqr = qn - Q[j];
+                        P2 = fmat(clh[j], epl, -crh[j] * epr);
+                        Q2 = fmat(clh[j], eql, -crh[j] * eqr);
+                        epl = epr;
+                        eql = eqr;
+                    }
                     const T yx = fmat(T(1.0 / 24.0), P2, fmat(T(-1.0 / 6.0), Q[j], fmat(T(-0.5), P[j], w[j])));
                     const T yw = fmat(T(1.0 / 24.0), Q2, fmat(T(1.0 / 6.0), P2, fmat(T(-0.5), Q[j], -P[j])));
                     comp_add(x[j], xl[j], yx);
@@ -287,10 +305,10 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
 }
 
-template <typename T, int DPL, int LPI, int METHOD>
+template <typename T, int DPL, int LPI, int METHOD, bool FREE>
 __global__ void __launch_bounds__(256) chain_kernel(ChainLaunch<T> a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    chain_run<T, DPL, LPI, METHOD>(a, g / LPI, (int)(g % LPI));
+    chain_run<T, DPL, LPI, METHOD, FREE>(a, g / LPI, (int)(g % LPI));
 }
 
 // Work list: lane group i integrates items[i] (an instance of any launch
@@ -326,9 +344,11 @@ template <typename T, int METHOD, int... I>
 constexpr auto make_table(std::integer_sequence<int, I...>) {
     struct Table {
         KernelFn<T, METHOD> f[sizeof...(I)];
+        KernelFn<T, METHOD> free_end[sizeof...(I)];   // LPI == 1 layouts with s == DPL
         ItemsFn<T, METHOD> g[sizeof...(I)];
     };
-    return Table{{&chain_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD>...},
+    return Table{{&chain_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD, false>...},
+                 {&chain_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD, kConfigs[I].lpi == 1>...},
                  {&chain_items_kernel<T, kConfigs[I].dpl, kConfigs[I].lpi, METHOD>...}};
 }
 
@@ -339,9 +359,11 @@ const auto &table() {
 }
 
 template <typename T, int METHOD>
-KernelFn<T, METHOD> lookup(ChainConfig cfg) {
+KernelFn<T, METHOD> lookup(ChainConfig cfg, int s) {
+    const bool free_end = cfg.lpi == 1 && s == cfg.dpl;
     for (int i = 0; i < kNumConfigs; ++i)
-        if (kConfigs[i].lpi == cfg.lpi && kConfigs[i].dpl == cfg.dpl) return table<T, METHOD>().f[i];
+        if (kConfigs[i].lpi == cfg.lpi && kConfigs[i].dpl == cfg.dpl)
+            return free_end ? table<T, METHOD>().free_end[i] : table<T, METHOD>().f[i];
     return nullptr;
 }
 
@@ -382,11 +404,11 @@ osc_status chain_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, hi
     const int64_t blocks = (threads + 255) / 256;
     if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "batch too large for one launch");
     if (method == OSC_RK4) {
-        auto f = lookup<T, OSC_RK4>(cfg);
+        auto f = lookup<T, OSC_RK4>(cfg, a.s);
         if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
         hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, a);
     } else {
-        auto f = lookup<T, OSC_VERLET>(cfg);
+        auto f = lookup<T, OSC_VERLET>(cfg, a.s);
         if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
         hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, a);
     }
