@@ -28,6 +28,7 @@
 // multiplied by at least one more power of the small step, use hi only.
 // FP64 runs the same code without the low parts.
 
+#include <cstdint>
 #include <type_traits>
 
 #include "osc_internal.h"
@@ -157,32 +158,68 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
     const double h = active ? a.c.h[b] : 1.0;
     const size_t plane = (size_t)a.batch * s;
 
+    // A lane's DPL consecutive elements of a [batch][s] plane move as 16-byte
+    // vectors when the run is whole and aligned, so that a wave's accesses
+    // to a plane fill whole cache lines together instead of one element per
+    // line per instruction (which lets lines leave the cache between the
+    // instructions that share them).
+    constexpr int V = 16 / (int)sizeof(T);
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    const bool run_whole = DPL % V == 0 && active && d0 + DPL <= s;
+    auto aligned = [&](const T *p) { return run_whole && ((uintptr_t)(p + base + d0) % 16) == 0; };
+    auto load = [&](const T *src, T (&dst)[DPL]) {
+        if (aligned(src)) {
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-        const int d = d0 + j;
-        const bool v = active && d < s;
-        const size_t i = base + d;
-        clh[j] = v ? a.c.clh[i] : T(0);
-        crh[j] = v ? a.c.crh[i] : T(0);
-        if constexpr (COMP) {
-            cll[j] = v ? a.c.cll[i] : T(0);
-            crl[j] = v ? a.c.crl[i] : T(0);
+            for (int q = 0; q < DPL / V; ++q) {
+                const vec_t v = *reinterpret_cast<const vec_t *>(src + base + d0 + q * V);
+#pragma unroll
+                for (int e = 0; e < V; ++e) dst[q * V + e] = v[e];
+            }
         } else {
-            cll[j] = T(0);
-            crl[j] = T(0);
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) dst[j] = (active && d0 + j < s) ? src[base + d0 + j] : T(0);
         }
-        if (a.load_mode == LOAD_USER) {
-            x[j] = v ? a.x0[i] : T(0);
+    };
+    auto store = [&](T *dst, const T (&src)[DPL]) {
+        if (aligned(dst)) {
+#pragma unroll
+            for (int q = 0; q < DPL / V; ++q) {
+                vec_t v;
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[e] = src[q * V + e];
+                *reinterpret_cast<vec_t *>(dst + base + d0 + q * V) = v;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j)
+                if (active && d0 + j < s) dst[base + d0 + j] = src[j];
+        }
+    };
+
+    load(a.c.clh, clh);
+    load(a.c.crh, crh);
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) cll[j] = crl[j] = T(0);
+    if constexpr (COMP) {
+        load(a.c.cll, cll);
+        load(a.c.crl, crl);
+    }
+    if (a.load_mode == LOAD_USER) {
+        T v0[DPL];
+        load(a.x0, x);
+        load(a.v0, v0);
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
             xl[j] = T(0);
-            const double wd = v ? h * (double)a.v0[i] : 0.0;
+            const double wd = h * (double)v0[j];
             w[j] = (T)wd;
             wl[j] = COMP ? (T)(wd - (double)w[j]) : T(0);
-        } else {
-            x[j] = v ? a.state[i] : T(0);
-            xl[j] = v ? a.state[plane + i] : T(0);
-            w[j] = v ? a.state[2 * plane + i] : T(0);
-            wl[j] = v ? a.state[3 * plane + i] : T(0);
         }
+    } else {
+        load(a.state, x);
+        load(a.state + plane, xl);
+        load(a.state + 2 * plane, w);
+        load(a.state + 3 * plane, wl);
     }
 
     const double invh = 1.0 / h;
@@ -206,13 +243,22 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
     const bool untouched = a.load_mode == LOAD_USER;
     auto write_frame = [&](int64_t f, bool initial) {
         const size_t fo = (size_t)f * plane;
+        T o[DPL];
+        if (a.xf) {
+            if (initial) load(a.x0, o);
+            else {
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            const int d = d0 + j;
-            if (active && d < s) {
-                if (a.xf) a.xf[fo + base + d] = initial ? a.x0[base + d] : (T)((double)x[j] + (double)xl[j]);
-                if (a.vf) a.vf[fo + base + d] = initial ? a.v0[base + d] : (T)vel(j);
+                for (int j = 0; j < DPL; ++j) o[j] = (T)((double)x[j] + (double)xl[j]);
             }
+            store(a.xf + fo, o);
+        }
+        if (a.vf) {
+            if (initial) load(a.v0, o);
+            else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) o[j] = (T)vel(j);
+            }
+            store(a.vf + fo, o);
         }
     };
 
@@ -286,20 +332,31 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
 
     bool ok = true;
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-        const int d = d0 + j;
-        if (!(active && d < s)) continue;
-        const size_t i = base + d;
-        ok = ok && finite(x[j]) && finite(w[j]);
-        if (a.store_mode & STORE_STATE) {
-            a.state[i] = x[j];
-            a.state[plane + i] = xl[j];
-            a.state[2 * plane + i] = w[j];
-            a.state[3 * plane + i] = wl[j];
+    for (int j = 0; j < DPL; ++j)
+        if (active && d0 + j < s) ok = ok && finite(x[j]) && finite(w[j]);
+    if (a.store_mode & STORE_STATE) {
+        store(a.state, x);
+        store(a.state + plane, xl);
+        store(a.state + 2 * plane, w);
+        store(a.state + 3 * plane, wl);
+    }
+    if (a.store_mode & STORE_USER) {
+        T o[DPL];
+        if (a.xe) {
+            if (copy_input) load(a.x0, o);
+            else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) o[j] = (T)((double)x[j] + (double)xl[j]);
+            }
+            store(a.xe, o);
         }
-        if (a.store_mode & STORE_USER) {
-            if (a.xe) a.xe[i] = copy_input ? a.x0[i] : (T)((double)x[j] + (double)xl[j]);
-            if (a.ve) a.ve[i] = copy_input ? a.v0[i] : (T)vel(j);
+        if (a.ve) {
+            if (copy_input) load(a.v0, o);
+            else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) o[j] = (T)vel(j);
+            }
+            store(a.ve, o);
         }
     }
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
