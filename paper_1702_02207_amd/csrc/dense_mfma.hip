@@ -22,6 +22,8 @@
 // instance is scaled by a power of two sigma so that |x| < 1 in FP16 terms;
 // powers of two keep every scaling exact.
 
+#include <cstdint>
+
 #include "osc_internal.h"
 
 namespace osc {
@@ -238,18 +240,38 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
         return wv * inv_sigma / h;
     };
     const bool untouched = a.load_mode == LOAD_USER;
+    // A lane's four consecutive DOFs of tile t go out as one 16-byte store
+    // when they are whole and aligned, so that a wave writes whole lines of
+    // each instance instead of one float per line per instruction.
+    auto emit = [&](float *dst, int t, auto val) {
+        if (!active) return;
+        const int row = row0 + 16 * t + 4 * quad;
+        float *p = dst + base + row;
+        if (row + 4 <= s && ((uintptr_t)p % 16) == 0) {
+            *reinterpret_cast<f4 *>(p) = f4{val(t, 0), val(t, 1), val(t, 2), val(t, 3)};
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (row + r < s) p[r] = val(t, r);
+        }
+    };
+    auto xout = [&](int t, int r) { return (float)(((double)x[t][r] + (double)xl[t][r][lane]) * inv_sigma); };
+    auto vout = [&](int t, int r) { return (float)vel(t, r); };
+    auto xin = [&](int t, int r) { return a.x0[base + row0 + 16 * t + 4 * quad + r]; };
+    auto vin = [&](int t, int r) { return a.v0[base + row0 + 16 * t + 4 * quad + r]; };
     auto write_frame = [&](int64_t f, bool initial) {
         const size_t fo = (size_t)f * a.frame_plane;
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = row0 + 16 * t + 4 * quad + r;
-                if (!(active && row < s)) continue;
-                const size_t i = base + row;
-                if (a.xf) a.xf[fo + i] = initial ? a.x0[i] : (float)(((double)x[t][r] + (double)xl[t][r][lane]) * inv_sigma);
-                if (a.vf) a.vf[fo + i] = initial ? a.v0[i] : (float)vel(t, r);
+        for (int t = 0; t < RT; ++t) {
+            if (a.xf) {
+                if (initial) emit(a.xf + fo, t, xin);
+                else emit(a.xf + fo, t, xout);
             }
+            if (a.vf) {
+                if (initial) emit(a.vf + fo, t, vin);
+                else emit(a.vf + fo, t, vout);
+            }
+        }
     };
 
     // RK4 coefficients in scaled units (ib = 1 / beta, a power of two)
@@ -337,20 +359,27 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = row0 + 16 * t + 4 * quad + r;
-            if (!(active && row < s)) continue;
-            const size_t i = base + row;
-            ok = ok && __builtin_isfinite(x[t][r]) && __builtin_isfinite(w[t][r]);
-            if (a.store_mode & STORE_STATE) {
-                a.state[i] = (float)((double)x[t][r] * inv_sigma);
-                a.state[plane + i] = (float)((double)xl[t][r][lane] * inv_sigma);
-                a.state[2 * plane + i] = (float)((double)w[t][r] * inv_sigma);
-                a.state[3 * plane + i] = (float)((double)wl[t][r][lane] * inv_sigma);
+            if (active && row < s) ok = ok && __builtin_isfinite(x[t][r]) && __builtin_isfinite(w[t][r]);
+        }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        if (a.store_mode & STORE_STATE) {
+            emit(a.state, t, [&](int tt, int r) { return (float)((double)x[tt][r] * inv_sigma); });
+            emit(a.state + plane, t, [&](int tt, int r) { return (float)((double)xl[tt][r][lane] * inv_sigma); });
+            emit(a.state + 2 * plane, t, [&](int tt, int r) { return (float)((double)w[tt][r] * inv_sigma); });
+            emit(a.state + 3 * plane, t, [&](int tt, int r) { return (float)((double)wl[tt][r][lane] * inv_sigma); });
+        }
+        if (a.store_mode & STORE_USER) {
+            if (a.xe) {
+                if (copy_input) emit(a.xe, t, xin);
+                else emit(a.xe, t, xout);
             }
-            if (a.store_mode & STORE_USER) {
-                if (a.xe) a.xe[i] = copy_input ? a.x0[i] : (float)(((double)x[t][r] + (double)xl[t][r][lane]) * inv_sigma);
-                if (a.ve) a.ve[i] = copy_input ? a.v0[i] : (float)vel(t, r);
+            if (a.ve) {
+                if (copy_input) emit(a.ve, t, vin);
+                else emit(a.ve, t, vout);
             }
         }
+    }
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
 }
 
