@@ -24,10 +24,17 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
+# Per-file code generation options.  The chain kernels keep a lane's whole
+# instance in registers and have DPL independent DOFs at every stage; the
+# register-pressure-first default schedule chains them one DOF at a time
+# (back-to-back dependent instructions), the ILP-first schedule interleaves
+# them (no dependent pair closer than ~10 instructions in the step loop).
+PER_FILE = {"chain.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *COMMON, "-c", src, "-o", obj]
+    cmd = ["hipcc", *COMMON, *PER_FILE.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

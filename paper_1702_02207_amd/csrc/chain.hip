@@ -273,12 +273,22 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
             const int64_t nf = (n / stride + 1) * stride;
             stop = nf < stop ? nf : stop;
         }
+        // FP32: the low parts collect the increments and are folded into the
+        // high parts every kNorm steps (at fixed global step indices, so any
+        // chunking of a run gives the same result); the products read
+        // x = hi + lo and w = hi + lo rounded once per step.
         auto step = [&]() {
+            T xe[DPL], we[DPL];
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                xe[j] = COMP ? x[j] + xl[j] : x[j];
+                we[j] = COMP ? w[j] + wl[j] : w[j];
+            }
             if constexpr (METHOD == OSC_RK4) {
                 T Q[DPL];
-                if constexpr (COMP) grp.apply2(x, clh, crh, cll, crl, P);
-                else grp.apply(x, clh, crh, P);
-                grp.apply(w, clh, crh, Q);
+                if constexpr (COMP) grp.apply2(xe, clh, crh, cll, crl, P);
+                else grp.apply(xe, clh, crh, P);
+                grp.apply(we, clh, crh, Q);
                 // P2 = B P and Q2 = B Q, formed per DOF as they are consumed
                 T pprev, pnext, qprev, qnext;
                 grp.halo(P, pprev, pnext);
@@ -299,31 +309,60 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
                         epl = epr;
                         eql = eqr;
                     }
-                    const T yx = fmat(T(1.0 / 24.0), P2, fmat(T(-1.0 / 6.0), Q[j], fmat(T(-0.5), P[j], w[j])));
+                    const T yx = fmat(T(1.0 / 24.0), P2, fmat(T(-1.0 / 6.0), Q[j], fmat(T(-0.5), P[j], we[j])));
                     const T yw = fmat(T(1.0 / 24.0), Q2, fmat(T(1.0 / 6.0), P2, fmat(T(-0.5), Q[j], -P[j])));
-                    comp_add(x[j], xl[j], yx);
-                    comp_add(w[j], wl[j], yw);
+                    if constexpr (COMP) {
+                        xl[j] += yx;
+                        wl[j] += yw;
+                    } else {
+                        x[j] += yx;
+                        w[j] += yw;
+                    }
                 }
             } else {
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) comp_add(x[j], xl[j], w[j]);
-                if constexpr (COMP) grp.apply2(x, clh, crh, cll, crl, P);
-                else grp.apply(x, clh, crh, P);
+                for (int j = 0; j < DPL; ++j) {
+                    if constexpr (COMP) xl[j] += we[j];
+                    else x[j] += we[j];
+                    xe[j] = COMP ? x[j] + xl[j] : x[j];
+                }
+                if constexpr (COMP) grp.apply2(xe, clh, crh, cll, crl, P);
+                else grp.apply(xe, clh, crh, P);
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) comp_add(w[j], wl[j], -P[j]);
+                for (int j = 0; j < DPL; ++j) {
+                    if constexpr (COMP) wl[j] -= P[j];
+                    else w[j] -= P[j];
+                }
+            }
+        };
+        // hi + lo <- the same sum with |lo| below half an ulp of hi (exact)
+        auto renorm = [&]() {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                T t = x[j] + xl[j];
+                xl[j] = xl[j] - (t - x[j]);
+                x[j] = t;
+                t = w[j] + wl[j];
+                wl[j] = wl[j] - (t - w[j]);
+                w[j] = t;
             }
         };
         // 32-bit trip counts keep the loop test on the scalar unit; two
         // steps per trip halve the loop overhead
+        constexpr int64_t kNorm = COMP ? 8 : (int64_t(1) << 30);
+        int64_t g = n;   // global index of the next step
         for (int64_t left = stop - n; left > 0;) {
-            const int cnt = (int)(left < (int64_t(1) << 30) ? left : (int64_t(1) << 30));
+            const int64_t to_norm = kNorm - g % kNorm;
+            const int cnt = (int)(left < to_norm ? left : to_norm);
             int k = 0;
             for (; k + 2 <= cnt; k += 2) {
                 step();
                 step();
             }
             if (k < cnt) step();
+            g += cnt;
             left -= cnt;
+            if (COMP && g % kNorm == 0) renorm();
         }
         n = stop;
         if (stride > 0 && n % stride == 0) write_frame(n / stride, false);
