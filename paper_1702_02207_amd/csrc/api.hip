@@ -301,26 +301,12 @@ osc_status integrate_split(osc_sys *s, const void *x0, const void *v0, int64_t n
                            void *xf, void *vf, void *xe, void *ve) {
     osc_status r = ensure_state(s);
     if (r) return r;
-    const size_t n = (size_t)s->batch * s->s;
-    if (!s->split_scratch) {
-        s->split_scratch = pool_alloc(2 * n * sizeof(T) + 64);
-        if (!s->split_scratch) return fail(OSC_ENOMEM, "device memory exhausted for the split dense path");
-    }
+    if ((r = sys_ensure_split_scratch(s))) return r;
     DenseSplitLaunch<T> a{};
-    a.batch = s->batch;
-    a.s = s->s;
-    a.shared = s->shared ? 1 : 0;
-    a.Bh = static_cast<const T *>(s->Bh);
-    a.Bl = static_cast<const T *>(s->Bl);
-    a.h = s->h;
-    a.state = static_cast<T *>(s->state);
-    a.P = static_cast<T *>(s->split_scratch);
-    a.Q = a.P + n;
-    a.counter = reinterpret_cast<int64_t *>(a.Q + n);
+    split_launch_base(s, a);
     a.out_stride = out_stride;
     a.xf = static_cast<T *>(xf);
     a.vf = static_cast<T *>(vf);
-    a.nonfinite = s->flag;
     // the graph replays phase kernels only: key on what they read
     static_assert(sizeof(DenseSplitLaunch<T>) <= sizeof(s->split_key), "graph key too small");
     unsigned char key[sizeof(s->split_key)] = {};
@@ -456,13 +442,32 @@ bool dense_uses_split(const osc_sys *s) { return use_split(s); }
 osc_status sys_ensure_state(osc_sys *s) { return ensure_state(s); }
 
 osc_status sys_ensure_split_scratch(osc_sys *s) {
-    const size_t n = (size_t)s->batch * s->s * (s->prec == OSC_F64 ? 8 : 4);
+    const size_t e = s->prec == OSC_F64 ? 8 : 4;
     if (!s->split_scratch) {
-        s->split_scratch = pool_alloc(2 * n + 64);
+        s->split_scratch = pool_alloc(dense_split_scratch_elems(s->s, s->batch) * e + 64);
         if (!s->split_scratch) return fail(OSC_ENOMEM, "device memory exhausted for the split dense path");
     }
     return OSC_OK;
 }
+
+template <typename T>
+void split_launch_base(osc_sys *s, DenseSplitLaunch<T> &a) {
+    const size_t n = (size_t)s->batch * s->s;
+    a.batch = s->batch;
+    a.s = s->s;
+    a.shared = s->shared ? 1 : 0;
+    a.groups = dense_split_groups(s->s, s->batch);
+    a.Bh = static_cast<const T *>(s->Bh);
+    a.Bl = static_cast<const T *>(s->Bl);
+    a.h = s->h;
+    a.state = static_cast<T *>(s->state);
+    a.P = static_cast<T *>(s->split_scratch);
+    a.part = a.P + n;
+    a.counter = reinterpret_cast<int64_t *>(a.part + 4 * (size_t)a.groups * n);
+    a.nonfinite = s->flag;
+}
+template void split_launch_base<float>(osc_sys *, DenseSplitLaunch<float> &);
+template void split_launch_base<double>(osc_sys *, DenseSplitLaunch<double> &);
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 

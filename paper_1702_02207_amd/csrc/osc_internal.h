@@ -174,17 +174,22 @@ struct DenseSplitLaunch {
     int64_t batch;
     int32_t s;
     int32_t shared;
+    int32_t groups;            // column groups: the k dimension of a product is split over this many workgroups
     const T *Bh, *Bl;
     const double *h;
     const T *x0, *v0;
     T *state;                  // [4][batch][s]
-    T *P, *Q;                  // [batch][s] products (Verlet: P carried between steps)
+    T *P;                      // [batch][s] Verlet: B x at the current step, carried between steps
+    T *part;                   // [4][batch][groups][s] partial products of each column group
     int64_t *counter;          // completed steps (device)
     int64_t nsteps, n0, out_stride;
     T *xf, *vf, *xe, *ve;
     int *nonfinite;
     int load_mode, store_mode;
 };
+// column groups of the split path for s and batch; scratch elements it needs
+int dense_split_groups(int s, int64_t batch);
+size_t dense_split_scratch_elems(int s, int64_t batch);
 template <typename T>
 osc_status dense_split_run(const DenseSplitLaunch<T> &a, int method, hipStream_t st, hipGraphExec_t *graph,
                            int64_t *graph_steps, int64_t graph_chunk);
@@ -221,6 +226,9 @@ ChainCoef<T> chain_coef(const osc_sys *s);
 bool dense_uses_split(const osc_sys *s);
 osc_status sys_ensure_state(osc_sys *s);
 osc_status sys_ensure_split_scratch(osc_sys *s);
+// the handle's part of a split-path launch (operator, state, scratch layout)
+template <typename T>
+void split_launch_base(osc_sys *s, DenseSplitLaunch<T> &a);
 void autotune_apply_cached(osc_sys *s);   // autotune.hip
 
 }  // namespace osc
@@ -252,7 +260,7 @@ struct osc_sys {
     // configuration (osc_set_config)
     int dense_kernel = 0;                // 0 auto, 1 VALU, 2 MFMA, 3 split
     int64_t graph_steps = 64;            // steps per captured hipGraph (split path), 0 = eager
-    void *split_scratch = nullptr;       // P, Q planes and the step counter
+    void *split_scratch = nullptr;       // carried P, partial products and the step counter
     hipGraphExec_t split_graph = nullptr;
     int64_t split_graph_len = 0;
     unsigned char split_key[256] = {};   // launch arguments the graph was captured with

@@ -88,7 +88,7 @@ int64_t estimate_bytes(const osc_desc &d, int64_t nframes) {
             const size_t fe = dense_mfma_fragment_elems((int)s) * 2;
             add(fe); add(fe);
         }
-        add(2 * s * e + 64);                                     // split scratch
+        add(dense_split_scratch_elems((int)s, 1) * e + 64);      // split scratch
     }
     return (int64_t)b;
 }
@@ -298,20 +298,10 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
             dense_smax[key] = std::max(dense_smax[key], (int)sy->s);
         } else {
             DenseSplitLaunch<T> a{};
-            a.batch = 1;
-            a.s = sy->s;
-            a.shared = 1;
-            a.Bh = static_cast<const T *>(sy->Bh);
-            a.Bl = static_cast<const T *>(sy->Bl);
-            a.h = sy->h;
-            a.state = static_cast<T *>(sy->state);
-            a.P = static_cast<T *>(sy->split_scratch);
-            a.Q = a.P + sy->s;
-            a.counter = reinterpret_cast<int64_t *>(a.Q + sy->s);
+            split_launch_base(sy, a);
             a.out_stride = r->out_stride;
             a.xf = static_cast<T *>(r->dxf);
             a.vf = static_cast<T *>(r->dvf);
-            a.nonfinite = sy->flag;
             a.x0 = static_cast<const T *>(r->dx0);
             a.v0 = static_cast<const T *>(r->dv0);
             a.xe = static_cast<T *>(r->dxe);
