@@ -8,6 +8,8 @@
 
 #include <type_traits>
 
+#include <algorithm>
+
 #include "osc_internal.h"
 
 namespace osc {
@@ -18,37 +20,50 @@ __device__ __forceinline__ void atomic_max_pos(double *addr, double v) {
     atomicMax(reinterpret_cast<unsigned long long *>(addr), __double_as_longlong(v));
 }
 
+// Grid-stride over the DOFs; the stability bound is reduced per workgroup so
+// that only one atomic per workgroup reaches the single bound in memory
+// (same-address atomics serialise in the cache).
 template <typename T>
-__global__ void chain_prepare_kernel(int64_t batch, int s, const double *__restrict__ m,
-                                     const double *__restrict__ k, const double *dt,
-                                     T *clh, T *crh, T *cll, T *crl, double *hout,
-                                     double *theta_bound, int *bad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= batch * (int64_t)s) return;
-    const int64_t b = i / s;
-    const int d = (int)(i % s);
-    const double h = dt[b];
-    const double mi = m[i];
-    const double kl = k[i];
-    const double kr = (d + 1 < s) ? k[i + 1] : 0.0;
-    const bool ok = (h > 0.0) && __builtin_isfinite(h) && (mi > 0.0) && __builtin_isfinite(mi) &&
-                    (kl >= 0.0) && __builtin_isfinite(kl) && (kr >= 0.0) && __builtin_isfinite(kr);
-    if (!ok) {
-        atomicOr(bad, 1);
-        return;
+__global__ void __launch_bounds__(256) chain_prepare_kernel(int64_t batch, int s, const double *__restrict__ m,
+                                                            const double *__restrict__ k, const double *dt, T *clh,
+                                                            T *crh, T *cll, T *crl, double *hout,
+                                                            double *theta_bound, int *bad) {
+    __shared__ double wmax[4];
+    double bound = 0.0;
+    const int64_t n = batch * (int64_t)s;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / s;
+        const int d = (int)(i - b * s);
+        const double h = dt[b];
+        const double mi = m[i];
+        const double kl = k[i];
+        const double kr = (d + 1 < s) ? k[i + 1] : 0.0;
+        const bool ok = (h > 0.0) && __builtin_isfinite(h) && (mi > 0.0) && __builtin_isfinite(mi) &&
+                        (kl >= 0.0) && __builtin_isfinite(kl) && (kr >= 0.0) && __builtin_isfinite(kr);
+        if (!ok) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        const double cl = h * h * kl / mi;
+        const double cr = h * h * kr / mi;
+        if (d == 0 && hout) hout[b] = h;
+        clh[i] = (T)cl;
+        crh[i] = (T)cr;
+        if constexpr (std::is_same<T, float>::value) {
+            cll[i] = (T)(cl - (double)clh[i]);
+            crl[i] = (T)(cr - (double)crh[i]);
+        }
+        // Gershgorin: every eigenvalue of B lies below the largest row sum
+        // |B_ii| + sum_j |B_ij| = 2 (cl_i + cr_i); theta = sqrt(lambda_max(B)) = h omega_max.
+        bound = fmax(bound, sqrt(2.0 * (cl + cr)));
     }
-    const double cl = h * h * kl / mi;
-    const double cr = h * h * kr / mi;
-    if (d == 0 && hout) hout[b] = h;
-    clh[i] = (T)cl;
-    crh[i] = (T)cr;
-    if constexpr (std::is_same<T, float>::value) {
-        cll[i] = (T)(cl - (double)clh[i]);
-        crl[i] = (T)(cr - (double)crh[i]);
+    for (int off = 32; off > 0; off >>= 1) bound = fmax(bound, __shfl_xor(bound, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = bound;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mx = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+        if (mx > 0.0) atomic_max_pos(theta_bound, mx);
     }
-    // Gershgorin: every eigenvalue of B lies below the largest row sum
-    // |B_ii| + sum_j |B_ij| = 2 (cl_i + cr_i); theta = sqrt(lambda_max(B)) = h omega_max.
-    atomic_max_pos(theta_bound, sqrt(2.0 * (cl + cr)));
 }
 
 // One group of G lanes (power of two <= 64) per instance; FP64 sums reduced
@@ -113,9 +128,8 @@ osc_status chain_prepare(int64_t batch, int s, const double *m, const double *k,
                          T *crh, T *cll, T *crl, double *h, double *theta_bound, int *bad_param,
                          hipStream_t st) {
     const int64_t n = batch * (int64_t)s;
-    const int64_t blocks = (n + 255) / 256;
     if (n == 0) return OSC_OK;
-    if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "batch * s too large");
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
     hipLaunchKernelGGL((chain_prepare_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, batch, s, m, k, dt,
                        clh, crh, cll, crl, h, theta_bound, bad_param);
     OSC_HIP(hipGetLastError());
