@@ -162,8 +162,9 @@ def test_dense_mfma_and_valu_agree_and_chunking_is_bitwise(method):
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
 @pytest.mark.parametrize("s,batch,shared", [(300, 1, True), (513, 2, False), (700, 1, True)])
 def test_dense_split_matches_oracle(method, prec, s, batch, shared):
-    """Large-s path: two kernels per step over many workgroups, replayed
-    from a captured hipGraph."""
+    """Large-s path: products split over row blocks and column groups of
+    workgroups (ragged last group at s = 300 and 513), three kernels per
+    step."""
     import torch
     from paper_1702_02207_amd import osc
     w = _dense_batch(500 + s, s, batch, 600, 100, shared=shared, vscale=0.01)
@@ -224,3 +225,29 @@ def test_per_instance_stability_check_covers_every_system():
     with pytest.raises(osc.OscError) as e:
         osc.System("dense", "rk4", "f32", M, K, dt, shared=False).create()
     assert e.value.status == osc.OSC_EUNSTABLE
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_dense_split_sixteen_groups_on_a_stream(method):
+    """s = 1024 (the most column groups: 16 of 64 columns), one instance, on
+    a stream of its own so that 64-step chunks replay a captured graph: 200
+    steps = three replays and 8 eager steps."""
+    import torch
+    from paper_1702_02207_amd import osc
+    s = 1024
+    w = _dense_batch(1024, s, 1, 200, 50, shared=True, vscale=0.01)
+    st = torch.cuda.Stream()
+    sysm = osc.System("dense", method, "f32", w.M, w.K, w.dt, shared=True, batch=1, stream=st).create()
+    x0 = torch.as_tensor(w.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    xf, vf, xe, ve = sysm.integrate(x0, v0, 200, 50)
+    sysm.sync()
+    xf, vf, xe, ve = [t.double().cpu().numpy() for t in (xf, vf, xe, ve)]
+    sysm.close()
+    x0r, v0r = f32_inputs(w)
+    rx, rv, rxe, rve = oracle_dense(method, w, x0=x0r, v0=v0r)
+    assert _err(xf, rx).max() < TOL_F32
+    assert _err(vf, rv).max() < TOL_F32
+    assert _err(xe, rxe).max() < TOL_F32
+    assert _err(ve, rve).max() < TOL_F32
