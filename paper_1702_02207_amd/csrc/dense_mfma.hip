@@ -7,9 +7,13 @@
 // the same rows of the 16 instances' state, kept in registers in the MFMA
 // accumulator layout (lane l, element r of row tile t: row 16 t + 4 (l/16) + r,
 // instance l % 16).  The operator stays resident in registers for the whole
-// launch; the right-hand operand of each product goes through a small padded
-// LDS buffer, which also performs the transpose from the accumulator layout
-// to the operand layout.
+// launch; the right-hand operand of each product goes through a small LDS
+// buffer, which also performs the transpose from the accumulator layout to
+// the operand layout.  The buffer is laid out [8-row block][instance][8 rows]:
+// an operand fragment (8 consecutive rows of one instance per lane) is one
+// 16-byte slot, and the 64 lanes of a fragment read, like the 4-row writes of
+// the accumulator layout, one contiguous stretch, so no two lanes of an access
+// meet in an LDS bank.
 //
 // Precision.  The FP16 operator B^ = beta h^2 A (beta a power of two with
 // ||B^||_inf <= 1) is split into B1 = fp16(B^) and B2 = fp16((B^ - B1) 2^11);
@@ -54,12 +58,12 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
     constexpr int kNW = NW;          // waves per workgroup
     constexpr int SP = 16 * RT * NW; // padded dimension
     constexpr int KS = SP / 32;      // k-steps of 32
-    constexpr int LD = SP + 8;       // LDS row stride (halfs) of one instance column
+    constexpr int NB = SP / 8;       // 8-row blocks of an operand
     // operand buffers: x (hi, lo), w (hi, lo), B x (hi, lo), B w (hi)
-    __shared__ __attribute__((aligned(16))) _Float16 bufA[2][kNC][LD];
-    __shared__ __attribute__((aligned(16))) _Float16 bufB[2][kNC][LD];
-    __shared__ __attribute__((aligned(16))) _Float16 bufC[2][kNC][LD];
-    __shared__ __attribute__((aligned(16))) _Float16 bufD[1][kNC][LD];
+    __shared__ __attribute__((aligned(16))) _Float16 bufA[2][NB][kNC][8];
+    __shared__ __attribute__((aligned(16))) _Float16 bufB[2][NB][kNC][8];
+    __shared__ __attribute__((aligned(16))) _Float16 bufC[2][NB][kNC][8];
+    __shared__ __attribute__((aligned(16))) _Float16 bufD[1][NB][kNC][8];
     __shared__ float smax[kNW][kNC];
     // compensation terms (touched once per step), lane-private slots
     __shared__ float sxl[kNW][RT][4][64];
@@ -143,7 +147,7 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
         }
 
     // operand u -> LDS (hi plane, optionally the scaled low plane)
-    auto put = [&](_Float16 (*buf)[kNC][LD], const float (&u)[RT][4], bool two) {
+    auto put = [&](_Float16 (*buf)[NB][kNC][8], const float (&u)[RT][4], bool two) {
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
             half4 hv, lv;
@@ -154,15 +158,15 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
                 lv[r] = (_Float16)((u[t][r] - (float)hh) * kSplit);
             }
             const int row = row0 + 16 * t + 4 * quad;
-            *reinterpret_cast<half4 *>(&buf[0][col][row]) = hv;
-            if (two) *reinterpret_cast<half4 *>(&buf[1][col][row]) = lv;
+            *reinterpret_cast<half4 *>(&buf[0][row / 8][col][row % 8]) = hv;
+            if (two) *reinterpret_cast<half4 *>(&buf[1][row / 8][col][row % 8]) = lv;
         }
     };
-    auto frag = [&](_Float16 (*buf)[kNC][LD], int p, int q) -> half8 {
-        return *reinterpret_cast<const half8 *>(&buf[p][col][32 * q + 8 * quad]);
+    auto frag = [&](_Float16 (*buf)[NB][kNC][8], int p, int q) -> half8 {
+        return *reinterpret_cast<const half8 *>(&buf[p][4 * q + quad][col][0]);
     };
     // three-term product: out = B^ u with u split in buf
-    auto prod3 = [&](_Float16 (*buf)[kNC][LD], float (&out)[RT][4]) {
+    auto prod3 = [&](_Float16 (*buf)[NB][kNC][8], float (&out)[RT][4]) {
         f4 am[RT], ac[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -185,7 +189,7 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
             for (int r = 0; r < 4; ++r) out[t][r] = __builtin_fmaf(ac[t][r], kUnsplit, am[t][r]);
     };
     // two-term product B1 (u1 + 2^-11 u2)
-    auto prod2 = [&](_Float16 (*buf)[kNC][LD], float (&out)[RT][4]) {
+    auto prod2 = [&](_Float16 (*buf)[NB][kNC][8], float (&out)[RT][4]) {
         f4 am[RT], ac[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
@@ -205,7 +209,7 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
 #pragma unroll
             for (int r = 0; r < 4; ++r) out[t][r] = __builtin_fmaf(ac[t][r], kUnsplit, am[t][r]);
     };
-    auto prod1 = [&](_Float16 (*buf)[kNC][LD], float (&out)[RT][4]) {
+    auto prod1 = [&](_Float16 (*buf)[NB][kNC][8], float (&out)[RT][4]) {
         f4 am[RT];
 #pragma unroll
         for (int t = 0; t < RT; ++t) am[t] = f4{0.f, 0.f, 0.f, 0.f};
