@@ -163,7 +163,7 @@ osc_status osc_dense_operator(osc_sys *sys, double *A);
  *                             across layouts.
  *   OSC_CFG_DENSE_KERNEL      dense: 0 automatic, 1 VALU, one workgroup per
  *                             instance (any s), 2 MFMA (FP32, shared operator,
- *                             s <= 256), 3 split (each step two kernels over
+ *                             s <= 256), 3 split (each step three kernels over
  *                             many workgroups; for few instances of large s).
  *   OSC_CFG_STEPS_PER_LAUNCH  maximum time steps per kernel launch (0 = the
  *                             whole run).  The state between launches keeps its

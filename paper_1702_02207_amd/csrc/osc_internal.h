@@ -167,7 +167,7 @@ osc_status dense_energy(int64_t batch, int s, int shared, const double *M, const
 template <typename T>
 osc_status dense_launch_vec(const DenseLaunch<T> &a, int method, hipStream_t st);
 
-// Large-s dense path (dense_split.hip): two kernels per step over many
+// Large-s dense path (dense_split.hip): three kernels per step over many
 // workgroups; state planes always in device memory.
 template <typename T>
 struct DenseSplitLaunch {
