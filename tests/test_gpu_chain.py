@@ -267,3 +267,37 @@ def test_autotune_dense_prefers_a_feasible_kernel():
     chosen = sysm.autotune(x0, torch.zeros_like(x0), probe_steps=50)
     sysm.close()
     assert chosen in (1, 2, 3)
+
+
+def _misaligned_like(t):
+    """A contiguous tensor like t whose data starts 4 bytes past a 16-byte boundary."""
+    import torch
+    buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+    out = buf[1:].view(t.shape)
+    out.copy_(t)
+    return out
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_misaligned_buffers_give_identical_results(method):
+    """Runs of DOFs move as 16-byte vectors only when aligned; buffers offset
+    by one float take the element-wise path and must give the same bits."""
+    import torch
+    from paper_1702_02207_amd import osc
+    rng = np.random.default_rng(37)
+    s, batch = 64, 9
+    m, k = workloads.random_chain(rng, batch, s)
+    dt = 0.01 / workloads.chain_omega_max(m, k)
+    sysm = osc.System("chain", method, "f32", m, k, dt).create()
+    x0 = torch.as_tensor(rng.normal(0, 0.1, (batch, s)), dtype=torch.float32, device="cuda")
+    v0 = torch.as_tensor(rng.normal(0, 1, (batch, s)), dtype=torch.float32, device="cuda") * 0.01
+    ref = [t.cpu().numpy() for t in sysm.integrate(x0, v0, 300, 100)]
+    xm, vm = _misaligned_like(x0), _misaligned_like(v0)
+    outs = tuple(_misaligned_like(torch.zeros_like(t)) for t in
+                 (torch.empty((4, batch, s), device="cuda"), torch.empty((4, batch, s), device="cuda"), x0, v0))
+    got = [t.cpu().numpy() for t in sysm.integrate(xm, vm, 300, 100, out=outs)]
+    sysm.sync()
+    sysm.close()
+    assert xm.data_ptr() % 16 != 0
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a, b)

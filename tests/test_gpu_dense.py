@@ -251,3 +251,31 @@ def test_dense_split_sixteen_groups_on_a_stream(method):
     assert _err(vf, rv).max() < TOL_F32
     assert _err(xe, rxe).max() < TOL_F32
     assert _err(ve, rve).max() < TOL_F32
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_mfma_misaligned_buffers_give_identical_results(method):
+    """The MFMA kernel moves four rows at a time as 16-byte vectors only when
+    aligned; buffers offset by one float must give the same bits."""
+    import torch
+    from paper_1702_02207_amd import osc
+
+    def misaligned_like(t):
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        out = buf[1:].view(t.shape)
+        out.copy_(t)
+        return out
+
+    w = _dense_batch(91, 64, 20, 300, 100, vscale=0.01)
+    sysm = osc.System("dense", method, "f32", w.M, w.K, w.dt, shared=True, batch=20).create()
+    sysm.set_config(osc.CFG_DENSE_KERNEL, 2)
+    x0 = torch.as_tensor(w.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=torch.float32, device="cuda")
+    ref = [t.cpu().numpy() for t in sysm.integrate(x0, v0, 300, 100)]
+    frames = torch.zeros((4, 20, 64), device="cuda")
+    outs = (misaligned_like(frames), misaligned_like(frames), misaligned_like(x0), misaligned_like(v0))
+    got = [t.cpu().numpy() for t in sysm.integrate(misaligned_like(x0), misaligned_like(v0), 300, 100, out=outs)]
+    sysm.sync()
+    sysm.close()
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a, b)
