@@ -43,20 +43,28 @@ __device__ __forceinline__ T fmat(T a, T b, T c) {
 }
 
 // Whole-wave DPP shifts: lane i receives lane i-1 (from_left) or lane i+1
-// (from_right); lanes shifted in from outside the wave receive 0.
-__device__ __forceinline__ int shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+// (from_right); a lane whose source lies outside the wave (lane 0 shifting
+// right, lane 63 shifting left) receives 0: with BC (bound_ctrl) set the
+// shift itself writes the 0, else the lane keeps the 0 it was given first.
+template <bool BC>
+__device__ __forceinline__ int shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, BC); }
+template <bool BC>
+__device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, BC); }
 
-__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, shr1(__builtin_bit_cast(int, v))); }
-__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, shl1(__builtin_bit_cast(int, v))); }
+template <bool BC>
+__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, shr1<BC>(__builtin_bit_cast(int, v))); }
+template <bool BC>
+__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, shl1<BC>(__builtin_bit_cast(int, v))); }
+template <bool BC>
 __device__ __forceinline__ double from_left(double v) {
     unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    unsigned lo = (unsigned)shr1((int)(unsigned)b), hi = (unsigned)shr1((int)(unsigned)(b >> 32));
+    unsigned lo = (unsigned)shr1<BC>((int)(unsigned)b), hi = (unsigned)shr1<BC>((int)(unsigned)(b >> 32));
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
+template <bool BC>
 __device__ __forceinline__ double from_right(double v) {
     unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    unsigned lo = (unsigned)shl1((int)(unsigned)b), hi = (unsigned)shl1((int)(unsigned)(b >> 32));
+    unsigned lo = (unsigned)shl1<BC>((int)(unsigned)b), hi = (unsigned)shl1<BC>((int)(unsigned)(b >> 32));
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
@@ -75,9 +83,17 @@ struct Group {
         if constexpr (LPI == 1) {
             prev = T(0);
             next = T(0);
+        } else if constexpr (LPI == 64 && DPL <= 16) {
+            // the group is the whole wave: the shifts already bring in 0
+            // (DPP folds into the extension's subtraction; no selects)
+            prev = from_left<true>(u[DPL - 1]);
+            next = from_right<true>(u[0]);
         } else {
-            T p = from_left(u[DPL - 1]);
-            T n = from_right(u[0]);
+            // groups inside the wave, and the 32-DOF lanes of the longest
+            // chains, whose kernels spill: there the form above computed
+            // wrong Verlet results, so they keep explicit selects
+            const T p = from_left<false>(u[DPL - 1]);
+            const T n = from_right<false>(u[0]);
             prev = first ? T(0) : p;
             next = last ? T(0) : n;
         }
