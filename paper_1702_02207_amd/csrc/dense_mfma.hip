@@ -20,9 +20,10 @@
 // an FP32 operand u becomes u1 = fp16(u) and u2 = fp16((u - u1) 2^11).  Then
 //   B^ u ~ B1 u1 + 2^-11 (B1 u2 + B2 u1)       (three MFMAs, ~2^-22 relative)
 // accumulates in FP32.  RK4 (exact linear Taylor form, as for chains) uses
-// this three-term product for B x and B w, two terms (B1 P1 + 2^-11 B1 P2)
-// for B P and one term for B Q: each later product enters the update
-// multiplied by a further power of the small step h omega.  The state of each
+// this three-term product for B x and B w and one term (B1 u1) for B P and
+// B Q: those two enter the update only at third order and beyond in
+// h omega <= 0.01, where the FP16 rounding (relative 2^-11) moves a frequency
+// by about 2^-11 (h omega)^2 / 12, far below the FP32 target.  The state of each
 // instance is scaled by a power of two sigma so that |x| < 1 in FP16 terms;
 // powers of two keep every scaling exact.
 
@@ -59,10 +60,10 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
     constexpr int SP = 16 * RT * NW; // padded dimension
     constexpr int KS = SP / 32;      // k-steps of 32
     constexpr int NB = SP / 8;       // 8-row blocks of an operand
-    // operand buffers: x (hi, lo), w (hi, lo), B x (hi, lo), B w (hi)
+    // operand buffers: x (hi, lo), w (hi, lo), B x (hi), B w (hi)
     __shared__ __attribute__((aligned(16))) _Float16 bufA[2][NB][kNC][8];
     __shared__ __attribute__((aligned(16))) _Float16 bufB[2][NB][kNC][8];
-    __shared__ __attribute__((aligned(16))) _Float16 bufC[2][NB][kNC][8];
+    __shared__ __attribute__((aligned(16))) _Float16 bufC[1][NB][kNC][8];
     __shared__ __attribute__((aligned(16))) _Float16 bufD[1][NB][kNC][8];
     __shared__ float smax[kNW][kNC];
     // compensation terms (touched once per step), lane-private slots
@@ -188,27 +189,6 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
 #pragma unroll
             for (int r = 0; r < 4; ++r) out[t][r] = __builtin_fmaf(ac[t][r], kUnsplit, am[t][r]);
     };
-    // two-term product B1 (u1 + 2^-11 u2)
-    auto prod2 = [&](_Float16 (*buf)[NB][kNC][8], float (&out)[RT][4]) {
-        f4 am[RT], ac[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-            am[t] = f4{0.f, 0.f, 0.f, 0.f};
-            ac[t] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int q = 0; q < KS; ++q) {
-            const half8 uh = frag(buf, 0, q), ul = frag(buf, 1, q);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) am[t] = mfma(B1r[t][q], uh, am[t]);
-#pragma unroll
-            for (int t = 0; t < RT; ++t) ac[t] = mfma(B1r[t][q], ul, ac[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) out[t][r] = __builtin_fmaf(ac[t][r], kUnsplit, am[t][r]);
-    };
     auto prod1 = [&](_Float16 (*buf)[NB][kNC][8], float (&out)[RT][4]) {
         f4 am[RT];
 #pragma unroll
@@ -309,7 +289,7 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
                         dx[t][r] = __builtin_fmaf(c1, T[t][r], w[t][r]);
                         dw[t][r] = d1 * T[t][r];
                     }
-                put(bufC, T, true);
+                put(bufC, T, false);
                 prod3(bufB, T);   // Q = B^ w
 #pragma unroll
                 for (int t = 0; t < RT; ++t)
@@ -320,7 +300,7 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
                     }
                 put(bufD, T, false);
                 __syncthreads();
-                prod2(bufC, T);   // P2 = B^ P
+                prod1(bufC, T);   // P2 = B^ P
 #pragma unroll
                 for (int t = 0; t < RT; ++t)
 #pragma unroll
