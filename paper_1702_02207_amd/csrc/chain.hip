@@ -1,14 +1,17 @@
 // Batched integration of fixed-free spring chains (eq. (2) generalised to s
 // bodies; s = 2 is the two-mass system itself) on gfx950.
 //
-// Layout.  A group of LPI consecutive lanes of one 64-wide wavefront holds
-// one instance; each lane keeps DPL consecutive degrees of freedom of that
-// instance in registers for the whole launch.  LPI = 1 is the
-// instance-per-lane layout (2-DOF ensembles), LPI = 64 one instance per
-// wavefront (long chains).  The only cross-lane traffic of the tridiagonal
-// stencil is the edge value of each neighbouring lane, fetched with DPP
-// whole-wave shifts (wave_shr:1 / wave_shl:1), so no LDS and no barrier is
-// used.  Many time steps run per launch; HBM is touched only to load the
+// Layout.  A group of LPI consecutive lanes holds one instance; each lane
+// keeps DPL consecutive degrees of freedom of that instance in registers for
+// the whole launch.  LPI = 1 is the instance-per-lane layout (2-DOF
+// ensembles), LPI = 64 one instance per 64-wide wavefront (long chains),
+// LPI = 128 one instance over the two wavefronts of a workgroup (chains of
+// 1025 to 2048 DOFs, which would not fit one wave's registers without
+// spilling).  The only cross-lane traffic of the tridiagonal stencil is the
+// edge value of each neighbouring lane, fetched with DPP whole-wave shifts
+// (wave_shr:1 / wave_shl:1); only the two-wave layout also passes the two
+// values across its wave boundary through LDS, with a workgroup barrier per
+// product.  Many time steps run per launch; HBM is touched only to load the
 // coefficients and state, to write frames and to store the final state.
 //
 // Arithmetic (scaled time tau = t/h, w = h v, B = h^2 A):
@@ -74,6 +77,13 @@ __device__ __forceinline__ double from_right(double v) {
 template <typename T, int DPL, int LPI, bool FREE>
 struct Group {
     bool first, last;   // lane is the first / last of its instance's group
+    int sl;             // lane within the group
+    // LPI == 128 (one instance over the two waves of a 128-thread workgroup):
+    // the values across the wave boundary go through LDS, in two slots used
+    // in turn, so that a slot is rewritten only after the barrier that
+    // follows every read of it
+    T *xch;
+    mutable int slot;
 
     // Neighbouring values across the lane boundary: the last DOF of the left
     // lane and the first DOF of the right lane.  Outside the chain the wall
@@ -83,19 +93,56 @@ struct Group {
         if constexpr (LPI == 1) {
             prev = T(0);
             next = T(0);
-        } else if constexpr (LPI == 64 && DPL <= 16) {
+        } else if constexpr (LPI == 64) {
             // the group is the whole wave: the shifts already bring in 0
             // (DPP folds into the extension's subtraction; no selects)
             prev = from_left<true>(u[DPL - 1]);
             next = from_right<true>(u[0]);
+        } else if constexpr (LPI == 128) {
+            T vp, vn;
+            halo_pair(u, u, prev, next, vp, vn);
         } else {
-            // groups inside the wave, and the 32-DOF lanes of the longest
-            // chains, whose kernels spill: there the form above computed
-            // wrong Verlet results, so they keep explicit selects
+            // groups inside the wave
             const T p = from_left<false>(u[DPL - 1]);
             const T n = from_right<false>(u[0]);
             prev = first ? T(0) : p;
             next = last ? T(0) : n;
+        }
+    }
+
+    // The halos of two vectors at once: for LPI == 128 within each wave as
+    // for LPI == 64, and across the boundary between the two waves through
+    // LDS with one barrier for both (every lane of the workgroup passes the
+    // barrier equally often: all run the same steps); otherwise two halos.
+    __device__ __forceinline__ void halo_pair(const T (&u)[DPL], const T (&v)[DPL], T &up, T &un, T &vp,
+                                              T &vn) const {
+        if constexpr (LPI == 128) {
+            up = from_left<true>(u[DPL - 1]);
+            un = from_right<true>(u[0]);
+            vp = from_left<true>(v[DPL - 1]);
+            vn = from_right<true>(v[0]);
+            T *const x = xch + 4 * slot;
+            slot ^= 1;
+            if (sl == 63) {
+                x[0] = u[DPL - 1];
+                x[2] = v[DPL - 1];
+            }
+            if (sl == 64) {
+                x[1] = u[0];
+                x[3] = v[0];
+            }
+            __syncthreads();
+            if (sl == 64) {
+                up = x[0];
+                vp = x[2];
+            }
+            if (sl == 63) {
+                un = x[1];
+                vn = x[3];
+            }
+        } else {
+            halo(u, up, un);
+            halo(v, vp, vn);
         }
     }
 
@@ -105,6 +152,11 @@ struct Group {
                                           T (&out)[DPL]) const {
         T prev, next;
         halo(u, prev, next);
+        apply_h(u, prev, next, cl, cr, out);
+    }
+    // the same with the halo given
+    __device__ __forceinline__ void apply_h(const T (&u)[DPL], const T prev, const T next, const T (&cl)[DPL],
+                                            const T (&cr)[DPL], T (&out)[DPL]) const {
         T el = u[0] - prev;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
@@ -125,6 +177,11 @@ struct Group {
                                            T (&out)[DPL]) const {
         T prev, next;
         halo(u, prev, next);
+        apply2_h(u, prev, next, clh, crh, cll, crl, out);
+    }
+    __device__ __forceinline__ void apply2_h(const T (&u)[DPL], const T prev, const T next,
+                                             const T (&clh)[DPL], const T (&crh)[DPL], const T (&cll)[DPL],
+                                             const T (&crl)[DPL], T (&out)[DPL]) const {
         T el = u[0] - prev;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
@@ -166,7 +223,12 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
     const bool active = b < a.batch;
     const int s = a.s;
     const int d0 = sl * DPL;
-    Group<T, DPL, LPI, FREE> grp{sl == 0, sl == LPI - 1};
+    T *xch = nullptr;
+    if constexpr (LPI == 128) {
+        __shared__ T xch_buf[8];
+        xch = xch_buf;
+    }
+    Group<T, DPL, LPI, FREE> grp{sl == 0, sl == LPI - 1, sl, xch, 0};
 
     T clh[DPL], crh[DPL], cll[DPL], crl[DPL];
     T x[DPL], xl[DPL], w[DPL], wl[DPL];
@@ -302,13 +364,21 @@ __device__ __forceinline__ void chain_run(const ChainLaunch<T> &a, const int64_t
             }
             if constexpr (METHOD == OSC_RK4) {
                 T Q[DPL];
-                if constexpr (COMP) grp.apply2(xe, clh, crh, cll, crl, P);
-                else grp.apply(xe, clh, crh, P);
-                grp.apply(we, clh, crh, Q);
+                if constexpr (LPI == 128) {
+                    // both halos across one barrier
+                    T xprev, xnext, wprev, wnext;
+                    grp.halo_pair(xe, we, xprev, xnext, wprev, wnext);
+                    if constexpr (COMP) grp.apply2_h(xe, xprev, xnext, clh, crh, cll, crl, P);
+                    else grp.apply_h(xe, xprev, xnext, clh, crh, P);
+                    grp.apply_h(we, wprev, wnext, clh, crh, Q);
+                } else {
+                    if constexpr (COMP) grp.apply2(xe, clh, crh, cll, crl, P);
+                    else grp.apply(xe, clh, crh, P);
+                    grp.apply(we, clh, crh, Q);
+                }
                 // P2 = B P and Q2 = B Q, formed per DOF as they are consumed
                 T pprev, pnext, qprev, qnext;
-                grp.halo(P, pprev, pnext);
-                grp.halo(Q, qprev, qnext);
+                grp.halo_pair(P, Q, pprev, pnext, qprev, qnext);
                 T epl = P[0] - pprev, eql = Q[0] - qprev;
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
@@ -429,7 +499,7 @@ template <typename T, int DPL, int LPI, int METHOD>
 __global__ void __launch_bounds__(256) chain_items_kernel(const ChainItem<T> *__restrict__ items, int64_t nitems) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = g / LPI;
-    if (i >= nitems) return;   // whole groups only: LPI divides the wave
+    if (i >= nitems) return;   // whole groups only: LPI divides the workgroup
     const ChainLaunch<T> a = items[i].L;
     chain_run<T, DPL, LPI, METHOD>(a, items[i].b, (int)(g % LPI));
 }
@@ -443,7 +513,7 @@ struct Entry {
 constexpr Entry kConfigs[] = {
     {1, 1}, {1, 2}, {1, 3}, {1, 4}, {1, 5}, {1, 6}, {1, 7}, {1, 8},
     {2, 8}, {4, 8}, {8, 8}, {16, 8}, {32, 8},
-    {64, 4}, {64, 8}, {64, 16}, {64, 32},
+    {64, 4}, {64, 8}, {64, 16}, {128, 16},
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -507,22 +577,28 @@ ChainConfig chain_pick_config(int s) {
     return best;
 }
 
+// Threads per workgroup: 256, except for instances spanning two waves, which
+// take a workgroup each (their halo exchange synchronises the workgroup, and
+// work-list items differ in their step counts).
+static int block_threads(ChainConfig cfg) { return cfg.lpi == 128 ? 128 : 256; }
+
 template <typename T>
 osc_status chain_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, hipStream_t st) {
     if ((long)cfg.lpi * cfg.dpl < a.s)
         return fail(OSC_EINVAL, "chain configuration too small for s");
     if (a.batch == 0) return OSC_OK;
+    const int bs = block_threads(cfg);
     const int64_t threads = a.batch * cfg.lpi;
-    const int64_t blocks = (threads + 255) / 256;
+    const int64_t blocks = (threads + bs - 1) / bs;
     if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "batch too large for one launch");
     if (method == OSC_RK4) {
         auto f = lookup<T, OSC_RK4>(cfg, a.s);
         if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
-        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(bs), 0, st, a);
     } else {
         auto f = lookup<T, OSC_VERLET>(cfg, a.s);
         if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
-        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(bs), 0, st, a);
     }
     OSC_HIP(hipGetLastError());
     return OSC_OK;
@@ -535,16 +611,17 @@ template <typename T>
 osc_status chain_launch_items(const ChainItem<T> *items, int64_t nitems, int method, ChainConfig cfg,
                               hipStream_t st) {
     if (nitems == 0) return OSC_OK;
-    const int64_t blocks = (nitems * cfg.lpi + 255) / 256;
+    const int bs = block_threads(cfg);
+    const int64_t blocks = (nitems * cfg.lpi + bs - 1) / bs;
     if (blocks > 0x7fffffff) return fail(OSC_EINVAL, "work list too long for one launch");
     if (method == OSC_RK4) {
         auto f = lookup_items<T, OSC_RK4>(cfg);
         if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
-        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, items, nitems);
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(bs), 0, st, items, nitems);
     } else {
         auto f = lookup_items<T, OSC_VERLET>(cfg);
         if (!f) return fail(OSC_ENOTSUP, "no chain kernel for this configuration");
-        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), 0, st, items, nitems);
+        hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(bs), 0, st, items, nitems);
     }
     OSC_HIP(hipGetLastError());
     return OSC_OK;

@@ -57,7 +57,7 @@ def test_c2_subset_fp32(method):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
 @pytest.mark.parametrize("s,batch", [(1, 3), (3, 67), (8, 5), (9, 33), (37, 7), (100, 5), (130, 3),
-                                     (513, 2), (1000, 3), (2048, 2)])
+                                     (513, 2), (1000, 3), (1025, 2), (1500, 3), (2048, 2)])
 def test_ragged_chains(method, prec, s, batch):
     rng = np.random.default_rng(1000 + s)
     m, k = workloads.random_chain(rng, batch, s)
@@ -199,7 +199,7 @@ def test_chain_layouts_and_chunking_are_bitwise_identical(method):
                              rng.normal(0, 1, (batch, s)) * 0.01 / dt[:, None], 600, 150)
     sysm = osc.System("chain", method, "f32", m, k, dt).create()
     ref = _run_chain(sysm, w, 600, 150)
-    for lpi, dpl in ((16, 8), (32, 8), (64, 4), (64, 8), (64, 16), (64, 32)):
+    for lpi, dpl in ((16, 8), (32, 8), (64, 4), (64, 8), (64, 16), (128, 16)):
         sysm.set_config(osc.CFG_CHAIN_LAYOUT, (lpi << 16) | dpl)
         got = _run_chain(sysm, w, 600, 150)
         for a, b in zip(ref, got):
