@@ -84,3 +84,36 @@ def test_continuous_admission():
         assert st["active"] >= 1            # the long request is still running
         long = srv.wait(long_t, timeout=120.0)
     assert short["latency_s"] < long["latency_s"]
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_long_chains_in_one_work_list(method):
+    """Chains of 1025-2048 DOFs (one instance over the two waves of a
+    workgroup, halo across them through LDS) with different step counts and
+    frame strides served together: each matches the oracle and is bitwise
+    the same as when served alone."""
+    rng = np.random.default_rng(21)
+    reqs = []
+    for s, nsteps, stride in ((1025, 900, 300), (1500, 1400, 700), (2048, 600, 200), (1777, 1100, 0)):
+        m, k = workloads.random_chain(rng, 1, s)
+        dt = 0.01 / workloads.chain_omega_max(m, k)
+        x0 = rng.normal(0, 0.1, s).astype(np.float32)
+        v0 = (rng.normal(0, 1.0, s) * 0.01 / dt[0]).astype(np.float32)
+        reqs.append((m[0], k[0], dt, x0, v0, nsteps, stride))
+    with osc.Server(max_slots=16, chunk_us=300) as srv:
+        tickets = [srv.submit("chain", method, "f32", *r) for r in reqs]
+        mixed = [srv.wait(t, timeout=120.0) for t in tickets]
+    for r, res in zip(reqs, mixed):
+        m, k, dt, x0, v0, nsteps, stride = r
+        rx, rv, rxe, rve = oracle.chain(method, m[None], k[None], dt, x0[None].astype(np.float64),
+                                        v0[None].astype(np.float64), nsteps, stride)
+        assert oracle.rel_traj_err(res["x_end"][None], rxe)[0] < 1e-5
+        assert oracle.rel_traj_err(res["v_end"][None], rve)[0] < 1e-5
+        if stride:
+            assert oracle.rel_traj_err(res["x_frames"][:, None, :], rx)[0] < 1e-5
+            assert oracle.rel_traj_err(res["v_frames"][:, None, :], rv)[0] < 1e-5
+    for r, res in zip(reqs, mixed):
+        with osc.Server(max_slots=4, chunk_us=300) as srv:
+            alone = srv.wait(srv.submit("chain", method, "f32", *r), timeout=120.0)
+        for key in ("x_end", "v_end"):
+            np.testing.assert_array_equal(alone[key], res[key])
