@@ -101,7 +101,7 @@ def test_two_mass_closed_form_is_modal_superposition():
 
 @pytest.mark.parametrize("x0", [(1.0, 0.0), (2.0, -3.0)])
 def test_c1_rk4_matches_closed_form(x0):
-    """configs[0]: eq. (3), m = 2, C = 2025, dt = 1e-5, 1e5 RK4 steps in FP64;
+    """The paper's two-mass system, eq. (3): m = 2, C = 2025, dt = 1e-5, 1e5 RK4 steps in FP64;
     (2, -3) are the initial conditions of the paper's MATLAB run (section 3)."""
     w = workloads.c1_paper_two_mass(x0=x0, out_stride=100)
     xf, vf, xe, ve = oracle.chain("rk4", w.m, w.k, w.dt, w.x0, w.v0, w.nsteps, w.out_stride)
