@@ -83,19 +83,59 @@ __device__ __forceinline__ T part_sum(const DenseSplitLaunch<T> &a, int q, int64
 // divided among the wavefronts and reduced through LDS.  Column j of the
 // operands is u1[j - uoff], u2[j - uoff].  Returns (lane = row):
 // y1 = Bh u1 (+ Bl u1 when LO), y2 = Bh u2.
-template <typename T, bool LO, bool TWO>
+// The wave's share of the group's columns: [k0, k1).
+__device__ __forceinline__ void wave_cols(int c0, int c1, int &k0, int &k1) {
+    const int wave = threadIdx.x >> 6;
+    const int per = (c1 - c0 + kWaves - 1) / kWaves;
+    k0 = c0 + wave * per;
+    k1 = min(c1, k0 + per);
+}
+
+// The first (up to) eight operator high parts of the lane's row in the
+// wave's columns, loaded ahead (their loads stay in flight while the caller
+// prepares the operands: a workgroup barrier waits for LDS traffic only).
+template <typename T>
+__device__ __forceinline__ void first_cols(const T *Bh, int s, int r0, int c0, int c1, T (&pre)[8]) {
+    const int row = r0 + (threadIdx.x & 63);
+    int k0, k1;
+    wave_cols(c0, c1, k0, k1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pre[q] = (row < s && k0 + q < k1) ? Bh[(size_t)(k0 + q) * s + row] : T(0);
+}
+
+template <typename T, bool LO, bool TWO, bool PRE = false>
 __device__ __forceinline__ void rows_product(const T *Bh, const T *Bl, int s, const T *u1, const T *u2, int uoff,
-                                             int r0, int c0, int c1, T &y1, T &y2, T (*red)[kWaves][kRows]) {
+                                             int r0, int c0, int c1, T &y1, T &y2, T (*red)[kWaves][kRows],
+                                             const T *pre = nullptr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = r0 + lane;
-    const int per = (c1 - c0 + kWaves - 1) / kWaves;
-    const int k0 = c0 + wave * per, k1 = min(c1, k0 + per);
+    int k0, k1;
+    wave_cols(c0, c1, k0, k1);
     // eight independent partial sums per product keep several loads in flight
     T a1[8], a1l[8], a2[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) a1[q] = a1l[q] = a2[q] = T(0);
     if (row < s) {
         int j = k0;
+        if constexpr (PRE) {
+            // the preloaded columns, in the order the loops below would take them
+            if (k0 + 8 <= k1) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    a1[q] = fmat(pre[q], u1[k0 + q - uoff], a1[q]);
+                    if constexpr (TWO) a2[q] = fmat(pre[q], u2[k0 + q - uoff], a2[q]);
+                }
+                j = k0 + 8;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (k0 + q < k1) {
+                        a1[0] = fmat(pre[q], u1[k0 + q - uoff], a1[0]);
+                        if constexpr (TWO) a2[0] = fmat(pre[q], u2[k0 + q - uoff], a2[0]);
+                    }
+                j = k1;
+            }
+        }
         for (; j + 8 <= k1; j += 8) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -170,6 +210,8 @@ __global__ void __launch_bounds__(kThreads) split_products2(DenseSplitLaunch<T> 
     const size_t ss = (size_t)s * s;
     const T *Bh = a.Bh + (a.shared ? 0 : b * ss);
     const int r0 = blockIdx.x * kRows, c0 = g * cg, c1 = min(s, c0 + cg);
+    T pre[8];
+    first_cols(Bh, s, r0, c0, c1, pre);
     for (int t = threadIdx.x; t < c1 - c0; t += kThreads) {
         sP[t] = part_sum(a, kP, b, c0 + t);
         sQ[t] = part_sum(a, kQ, b, c0 + t);
@@ -178,7 +220,7 @@ __global__ void __launch_bounds__(kThreads) split_products2(DenseSplitLaunch<T> 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = r0 + lane;
     T y1, y2;
-    rows_product<T, false, true>(Bh, nullptr, s, sP, sQ, c0, r0, c0, c1, y1, y2, red);
+    rows_product<T, false, true, true>(Bh, nullptr, s, sP, sQ, c0, r0, c0, c1, y1, y2, red, pre);
     if (wave == 0 && row < s) {
         a.part[part_at(a, kP2, b, g, row)] = y1;
         a.part[part_at(a, kQ2, b, g, row)] = y2;
