@@ -78,8 +78,11 @@ typedef enum { OSC_MEM_HOST = 0, OSC_MEM_DEVICE = 1 } osc_mem;
  * read during osc_create only; the caller may free them afterwards.
  *
  * prec = OSC_F32 keeps the state in FP32 with compensated (two-term) updates
- * and coefficients split into FP32 high + low parts; dense products run on
- * MFMA with FP16 operands split into three terms (FP32 accumulation).
+ * and coefficients split into FP32 high + low parts; dense products with a
+ * shared operator (s <= 256) run on MFMA with the operator and operands split
+ * into FP16 high and scaled low parts (three terms for B x, two for B w, one
+ * for the higher-order products; FP32 accumulation); results stay within the
+ * FP32 tolerance of the FP64 reference.
  * prec = OSC_F64 runs everything in double.
  */
 typedef struct osc_desc {
