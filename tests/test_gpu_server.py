@@ -117,3 +117,30 @@ def test_long_chains_in_one_work_list(method):
             alone = srv.wait(srv.submit("chain", method, "f32", *r), timeout=120.0)
         for key in ("x_end", "v_end"):
             np.testing.assert_array_equal(alone[key], res[key])
+
+
+def test_full_stream_sampled_parity():
+    """The served stream at its full size (200 requests, s up to 2048, up to
+    1e5 steps, all submitted at once), in the server configuration bench.py
+    times; a sample of requests the oracle can integrate in seconds (the
+    cheapest chains and dense systems, the longest chain and the cheapest
+    dense system of s > 256 within that budget) is compared frame by frame
+    at the FP32 tolerance."""
+    reqs = workloads.c5_request_stream(n_requests=200, qps=1e6)
+    with osc.Server(max_slots=64) as srv:
+        tickets = [_submit(srv, r) for r in reqs]
+        results = [srv.wait(t, timeout=300.0) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    cost = lambda r: r.system.s * r.system.nsteps * (r.system.s if r.kind == "dense" else 8)
+    chains = sorted((r for r in reqs if r.kind == "chain"), key=cost)
+    dense = sorted((r for r in reqs if r.kind == "dense"), key=cost)
+    longest = max((r for r in chains if cost(r) <= 4e9), key=lambda r: r.system.s)
+    large = [r for r in dense if r.system.s > 256 and cost(r) <= 4e9][:1]   # the split path
+    sample = {r.rid: r for r in chains[:3] + dense[:2] + [longest] + large}
+    for rid, r in sample.items():
+        res = results[rid]
+        rx, rv = _oracle(r)
+        ex = oracle.rel_traj_err(res["x_frames"][:, None, :], rx[:, None, :])[0]
+        ev = oracle.rel_traj_err(res["v_frames"][:, None, :], rv[:, None, :])[0]
+        assert ex < 1e-5 and ev < 1e-5, (r.kind, r.system.s, r.system.nsteps, ex, ev)
