@@ -186,6 +186,25 @@ def test_dense_split_matches_oracle(method, prec, s, batch, shared):
 
 
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_dense_largest_size_against_modal_solution(method):
+    """s = 2048, the largest size the library takes: formation of A and the
+    automatic kernel choice (the split path, sixteen column groups), 200
+    steps with frames, against the exact discrete solution of the scheme per
+    normal mode (LAPACK eigh of (K, M); the same closed form pins the FP64
+    oracle, whose unblocked Cholesky alone needs minutes at this size)."""
+    from oracle import closed_form as cf
+    w = _dense_batch(2701, 2048, 1, 200, 50, shared=True, vscale=0.01)
+    xf, vf, xe, ve = gpu_dense(method, "f32", w)
+    x0, v0 = f32_inputs(w)
+    n = np.arange(0, 201, 50)
+    exact = cf.rk4_discrete if method == "rk4" else cf.verlet_discrete
+    rx, rv = exact(n, w.dt[0], w.M, w.K, x0[0], v0[0])
+    assert _err(xf, rx[:, None, :]).max() < TOL_F32
+    assert _err(vf, rv[:, None, :]).max() < TOL_F32
+    np.testing.assert_array_equal(xf[-1], xe)
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
 def test_dense_split_graph_replays_match_eager(method):
     """Every replay of the captured step graph, with other eager GPU work and
     synchronisations in between, equals the eagerly launched run bitwise."""
