@@ -185,6 +185,32 @@ def test_dense_split_matches_oracle(method, prec, s, batch, shared):
     assert _err(ve, rve).max() < tol
 
 
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_rest_state_stays_at_rest(method, kernel):
+    """An instance at rest (x0 = v0 = 0) among moving ones stays exactly at
+    rest on every dense kernel (the MFMA path's per-instance scale falls back
+    to 1 for an all-zero state); the others match the oracle."""
+    import torch
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(77, 64, 20, 300, 100, vscale=0.01)
+    w.x0[3] = 0.0
+    w.v0[3] = 0.0
+    sysm = osc.System("dense", method, "f32", w.M, w.K, w.dt, shared=True, batch=20).create()
+    sysm.set_config(osc.CFG_DENSE_KERNEL, kernel)
+    x0 = torch.as_tensor(w.x0, dtype=torch.float32, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=torch.float32, device="cuda")
+    xf, vf, xe, ve = [t.double().cpu().numpy() for t in sysm.integrate(x0, v0, w.nsteps, w.out_stride)]
+    sysm.sync()
+    sysm.close()
+    assert not xf[:, 3].any() and not vf[:, 3].any() and not xe[3].any() and not ve[3].any()
+    x0r, v0r = f32_inputs(w)
+    rx, rv, _, _ = oracle_dense(method, w, x0=x0r, v0=v0r)
+    keep = [b for b in range(20) if b != 3]
+    assert _err(xf[:, keep], rx[:, keep]).max() < TOL_F32
+    assert _err(vf[:, keep], rv[:, keep]).max() < TOL_F32
+
+
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
 def test_dense_largest_size_against_modal_solution(method):
     """s = 2048, the largest size the library takes: formation of A and the
