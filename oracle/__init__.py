@@ -51,8 +51,9 @@ def _load():
     lib.oracle_energy_chain.argtypes = [i64, i32, d, d, d, d, d]
     lib.oracle_energy_dense.argtypes = [i64, i32, i32, d, d, d, d, d]
     lib.oracle_verlet_q_chain.argtypes = [i64, i32, d, d, d, d, d, d]
+    lib.oracle_verlet_q_dense.argtypes = [i64, i32, i32, d, d, d, d, d, d]
     for f in ("oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
-              "oracle_energy_dense", "oracle_verlet_q_chain"):
+              "oracle_energy_dense", "oracle_verlet_q_chain", "oracle_verlet_q_dense"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -150,6 +151,18 @@ def verlet_q_chain(m, k, dt, x, v):
     Q = np.empty(batch)
     _check(lib.oracle_verlet_q_chain(batch, s, _p(m), _p(k), _p(dt), _p(x), _p(v), _p(Q)),
            "verlet_q_chain")
+    return Q
+
+
+def verlet_q_dense(M, K, dt, x, v, shared=True):
+    """Q = v^T M v + x^T K x - (dt^2/4) (K x)^T M^-1 (K x) per instance, the
+    exact invariant of velocity Verlet for a dense system."""
+    lib = _load()
+    M, K, dt, x, v = map(_f64, (M, K, np.atleast_1d(dt), x, v))
+    batch, s = x.shape
+    Q = np.empty(batch)
+    _check(lib.oracle_verlet_q_dense(batch, s, 1 if shared else 0, _p(M), _p(K), _p(dt), _p(x), _p(v),
+                                     _p(Q)), "verlet_q_dense")
     return Q
 
 

@@ -352,3 +352,47 @@ int oracle_verlet_q_chain(int64_t batch, int s, const double *m, const double *k
     free(a);
     return ORC_OK;
 }
+
+/* Verlet invariant for dense systems (eq. (1) with full M, K): with f = K x
+ * and A = M^-1 K formed by Cholesky as above, (K x)^T M^-1 (K x) = f^T (A x),
+ * so Q = v^T M v + x^T K x - (h^2/4) f^T (A x).  M, K shared [s][s] (dt[0])
+ * or per instance [batch][s][s] (dt[b]). */
+int oracle_verlet_q_dense(int64_t batch, int s, int shared, const double *M, const double *K,
+                          const double *dt, const double *x, const double *v, double *Q) {
+    if (batch < 0 || s < 1) return ORC_EINVAL;
+    const size_t ss = (size_t)s * s;
+    double *A = (double *)malloc(sizeof(double) * ss);
+    double *f = (double *)malloc(sizeof(double) * s);
+    double *ax = (double *)malloc(sizeof(double) * s);
+    if (!A || !f || !ax) { free(A); free(f); free(ax); return ORC_ENOMEM; }
+    int st = ORC_OK;
+    for (int64_t b = 0; b < batch && st == ORC_OK; ++b) {
+        const double *Mb = shared ? M : M + b * ss, *Kb = shared ? K : K + b * ss;
+        if (b == 0 || !shared) st = oracle_form_a(s, Mb, Kb, A);
+        if (st) break;
+        const double *xb = x + b * s, *vb = v + b * s;
+        const double h = shared ? dt[0] : dt[b];
+        double kin = 0.0, pot = 0.0, corr = 0.0;
+        for (int i = 0; i < s; ++i) {
+            double fi = 0.0, ai = 0.0;
+            for (int j = 0; j < s; ++j) {
+                fi += Kb[(size_t)i * s + j] * xb[j];
+                ai += A[(size_t)i * s + j] * xb[j];
+            }
+            f[i] = fi;
+            ax[i] = ai;
+        }
+        for (int i = 0; i < s; ++i) {
+            for (int j = 0; j < s; ++j) {
+                kin += vb[i] * Mb[(size_t)i * s + j] * vb[j];
+                pot += xb[i] * Kb[(size_t)i * s + j] * xb[j];
+            }
+            corr += f[i] * ax[i];
+        }
+        Q[b] = kin + pot - 0.25 * h * h * corr;
+    }
+    free(A);
+    free(f);
+    free(ax);
+    return st;
+}

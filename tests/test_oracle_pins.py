@@ -233,6 +233,89 @@ def test_verlet_shadow_invariant_conserved():
     assert np.abs(E / E[0] - 1).max() > 1e-4       # plain E is not the conserved quantity
 
 
+def _dense_system(seed, s):
+    rng = np.random.default_rng(seed)
+    M, K = workloads.random_dense_system(rng, s)
+    wmax = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    return rng, M, K, wmax
+
+
+def test_verlet_shadow_invariant_dense_conserved():
+    """Q = v'Mv + x'Kx - (h^2/4)(Kx)'M^-1(Kx) stays constant along the oracle's
+    own dense Verlet trajectory while the plain energy does not."""
+    rng, M, K, wmax = _dense_system(31, 9)
+    h = 0.3 / wmax
+    x0, v0 = rng.normal(size=(2, 9)), rng.normal(size=(2, 9)) * wmax
+    xf, vf, _, _ = oracle.dense("verlet", M, K, [h], x0, v0, 2000, 50)
+    Q = np.array([oracle.verlet_q_dense(M, K, [h], xf[f], vf[f]) for f in range(len(xf))])
+    E = np.array([oracle.energy_dense(M, K, xf[f], vf[f]) for f in range(len(xf))])
+    assert np.abs(Q / Q[0] - 1).max() < 1e-12
+    assert np.abs(E / E[0] - 1).max() > 1e-4
+
+
+def test_verlet_shadow_invariant_dense_modal_form():
+    """With M-orthonormal modes (q = phi'Mx, p = phi'Mv), Q is the sum over
+    modes of p^2 + w^2 q^2 (1 - (w h)^2 / 4): LAPACK eigenpairs, not the
+    oracle's Cholesky route.  Per-instance systems give the same as shared."""
+    rng, M, K, wmax = _dense_system(32, 7)
+    h = 0.7 / wmax
+    x, v = rng.normal(size=(3, 7)), rng.normal(size=(3, 7))
+    w, phi = cf.modes(M, K)
+    q, p = x @ M @ phi, v @ M @ phi
+    ref = np.sum(p ** 2 + (w * q) ** 2 * (1.0 - (w * h) ** 2 / 4.0), axis=1)
+    got = oracle.verlet_q_dense(M, K, [h], x, v)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+    got_pi = oracle.verlet_q_dense(np.stack([M] * 3), np.stack([K] * 3), [h] * 3, x, v, shared=False)
+    np.testing.assert_allclose(got_pi, ref, rtol=1e-12)
+
+
+def test_verlet_shadow_invariant_dense_equals_chain_form():
+    rng = np.random.default_rng(33)
+    s = 11
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    h = 0.5 / np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    x, v = rng.normal(size=(2, s)), rng.normal(size=(2, s))
+    Qc = oracle.verlet_q_chain(np.tile(m, (2, 1)), np.tile(k, (2, 1)), [h, h], x, v)
+    Qd = oracle.verlet_q_dense(M, K, [h], x, v)
+    np.testing.assert_allclose(Qd, Qc, rtol=1e-12)
+
+
+Q_MUTANTS = [
+    ("Q[b] = kin + pot - 0.25 * h * h * corr;", "Q[b] = kin + pot + 0.25 * h * h * corr;"),   # sign
+    ("Q[b] = kin + pot - 0.25 * h * h * corr;", "Q[b] = kin + pot - 0.5 * h * h * corr;"),    # factor
+    ("ai += A[(size_t)i * s + j] * xb[j];", "ai += A[(size_t)j * s + i] * xb[j];"),           # transposed A
+    ("fi += Kb[(size_t)i * s + j] * xb[j];", "fi += Mb[(size_t)i * s + j] * xb[j];"),         # wrong matrix
+]
+
+
+@pytest.mark.parametrize("orig,mut", Q_MUTANTS)
+def test_pins_catch_planted_dense_invariant_mistakes(orig, mut, tmp_path):
+    """Recompile the oracle with one plausible mistake in the dense invariant
+    and check that the modal closed form rejects it (CPU only)."""
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "osc_oracle.c")).read()
+    assert orig in src
+    mpath = tmp_path / "mut.c"
+    mpath.write_text(src.replace(orig, mut))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(mpath), "-lm"], check=True)
+    import ctypes
+    L = ctypes.CDLL(str(lib))
+    d = ctypes.POINTER(ctypes.c_double)
+    L.oracle_verlet_q_dense.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, d, d, d, d, d, d]
+    rng, M, K, wmax = _dense_system(34, 6)
+    h = 0.7 / wmax
+    x, v = rng.normal(size=(1, 6)), rng.normal(size=(1, 6))
+    w, phi = cf.modes(M, K)
+    q, p = x @ M @ phi, v @ M @ phi
+    ref = np.sum(p ** 2 + (w * q) ** 2 * (1.0 - (w * h) ** 2 / 4.0), axis=1)
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in (M, K, [h], x, v)]
+    Q = np.empty(1)
+    L.oracle_verlet_q_dense(1, 6, 1, *[a.ctypes.data_as(d) for a in args], Q.ctypes.data_as(d))
+    assert not np.allclose(Q, ref, rtol=1e-12), "planted mistake not detected"
+
+
 def test_rk4_energy_decay_matches_amplification():
     rng = np.random.default_rng(4)
     s = 4
