@@ -126,35 +126,63 @@ class System:
     def __init__(self, kind: str, method: str, prec: str, M, K, dt, shared: bool = True,
                  batch: Optional[int] = None, stream=None):
         import torch
-        lib = load()
+        load()
+        if kind not in KINDS or method not in METHODS or prec not in PRECS:
+            raise ValueError(f"unknown kind/method/precision {kind!r}/{method!r}/{prec!r}")
         self.kind, self.method, self.prec = kind, method, prec
         self.dtype = torch.float64 if prec == "f64" else torch.float32
         on_device = isinstance(M, torch.Tensor)
+        if on_device != isinstance(K, torch.Tensor):
+            raise ValueError("M and K must both be host arrays or both be device tensors")
         if on_device:
-            self._keep = [t.contiguous().to(torch.float64) for t in (M, K, dt)]
-            ptrs = [t.data_ptr() for t in self._keep]
-            M_shape = tuple(M.shape)
+            if not (M.is_cuda and K.is_cuda):
+                raise ValueError("device parameters must be CUDA tensors")
+            dt = dt if isinstance(dt, torch.Tensor) else torch.as_tensor(np.atleast_1d(dt), device=M.device)
+            arrs = [t.contiguous().to(torch.float64) for t in (M, K, dt.reshape(-1))]
         else:
-            self._keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (M, K, np.atleast_1d(dt))]
-            ptrs = [a.ctypes.data for a in self._keep]
-            M_shape = self._keep[0].shape
+            arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (M, K, np.ravel(dt))]
+        M_shape, K_shape, ndt = tuple(arrs[0].shape), tuple(arrs[1].shape), int(arrs[2].shape[0])
+        given_batch = batch
         if kind == "chain":
+            if len(M_shape) != 2 or K_shape != M_shape:
+                raise ValueError(f"chain M and K must both be [batch, s]; got {M_shape} and {K_shape}")
             batch, s = M_shape
             shared = False
+            want_dt = batch
         elif shared:
+            if len(M_shape) != 2 or M_shape[0] != M_shape[1] or K_shape != M_shape:
+                raise ValueError(f"shared dense M and K must both be [s, s]; got {M_shape} and {K_shape}")
             s = M_shape[0]
+            want_dt = 1
         else:
+            if len(M_shape) != 3 or M_shape[1] != M_shape[2] or K_shape != M_shape:
+                raise ValueError(f"per-instance dense M and K must be [batch, s, s]; got {M_shape} and {K_shape}")
             batch, s = M_shape[0], M_shape[1]
+            want_dt = batch
+        if given_batch is not None and int(given_batch) != batch:
+            raise ValueError(f"batch {given_batch} disagrees with the parameters' {batch} instances")
+        if ndt == 1 and want_dt != 1:
+            # one step for every instance
+            arrs[2] = (arrs[2].expand(want_dt).contiguous() if on_device
+                       else np.full(want_dt, arrs[2][0], dtype=np.float64))
+        elif ndt != want_dt:
+            raise ValueError(f"dt must hold 1 or {want_dt} values; got {ndt}")
+        if batch is None or int(batch) < 0:
+            raise ValueError("batch must be given (>= 0) for a shared dense system")
+        self._keep = arrs
+        ptrs = [t.data_ptr() for t in arrs] if on_device else [a.ctypes.data for a in arrs]
         self.s = int(s)
+        self.batch = int(batch)
         self._shared = shared
         self.stream = stream
-        self._desc = Desc(KINDS[kind], METHODS[method], PRECS[prec], self.s,
-                          int(batch if batch is not None else 0), 1 if shared else 0,
+        self._desc = Desc(KINDS[kind], METHODS[method], PRECS[prec], self.s, self.batch, 1 if shared else 0,
                           MEM_DEVICE if on_device else MEM_HOST, ptrs[0], ptrs[1], ptrs[2])
         self.handle = None
 
     def create(self, batch: Optional[int] = None):
         if batch is not None:
+            if not (self.kind == "dense" and self._shared):
+                raise ValueError("batch is fixed by the parameters except for a shared dense system")
             self._desc.batch = int(batch)
         lib = load()
         h = ctypes.c_void_p()
@@ -165,19 +193,30 @@ class System:
         return self
 
     # -- helpers -----------------------------------------------------------
-    def _state(self, t):
+    def _tensor(self, t, shape, dtype, what):
         import torch
-        assert isinstance(t, torch.Tensor) and t.is_cuda, "state must be a CUDA tensor"
-        assert t.dtype == self.dtype and t.is_contiguous(), "state dtype/layout mismatch"
-        assert tuple(t.shape) == (self.batch, self.s), f"state shape {tuple(t.shape)} != {(self.batch, self.s)}"
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise ValueError(f"{what} must be a CUDA tensor")
+        if t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous {dtype} tensor; got {t.dtype}"
+                             f"{'' if t.is_contiguous() else ' (not contiguous)'}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
         return t
+
+    def _state(self, t, what="state"):
+        if self.handle is None:
+            raise ValueError("the system has not been created (call create())")
+        return self._tensor(t, (self.batch, self.s), self.dtype, what)
 
     def integrate(self, x0, v0, nsteps: int, out_stride: int = 0, frames: bool = True,
                   out=None):
         """Returns (x_frames, v_frames, x_end, v_end) as new device tensors
         (frames None when out_stride == 0 or frames is False)."""
         import torch
-        x0, v0 = self._state(x0), self._state(v0)
+        x0, v0 = self._state(x0, "x0"), self._state(v0, "v0")
+        if nsteps < 0 or out_stride < 0:
+            raise ValueError("nsteps and out_stride must be >= 0")
         nf = nsteps // out_stride + 1 if (out_stride > 0 and frames) else 0
         dev = x0.device
         if out is None:
@@ -187,6 +226,15 @@ class System:
             ve = torch.empty_like(v0)
         else:
             xf, vf, xe, ve = out
+            fshape = (nf, self.batch, self.s)
+            for t, what in ((xf, "x_frames"), (vf, "v_frames")):
+                if t is not None:
+                    if not nf:
+                        raise ValueError(f"{what} given but no frames are produced")
+                    self._tensor(t, fshape, self.dtype, what)
+            for t, what in ((xe, "x_end"), (ve, "v_end")):
+                if t is not None:
+                    self._state(t, what)
         _check(load().osc_integrate(self.handle, _dptr(x0), _dptr(v0), int(nsteps),
                                     int(out_stride) if nf else 0, _dptr(xf), _dptr(vf),
                                     _dptr(xe), _dptr(ve)))
@@ -194,7 +242,9 @@ class System:
 
     def integrate_plain(self, x0, v0, nsteps: int):
         import torch
-        x0, v0 = self._state(x0), self._state(v0)
+        x0, v0 = self._state(x0, "x0"), self._state(v0, "v0")
+        if nsteps < 0:
+            raise ValueError("nsteps must be >= 0")
         xe, ve = torch.empty_like(x0), torch.empty_like(v0)
         _check(load().osc_integrate_plain(self.handle, _dptr(x0), _dptr(v0), int(nsteps),
                                           _dptr(xe), _dptr(ve)))
@@ -276,6 +326,18 @@ class Server:
         x0 = np.ascontiguousarray(np.ravel(x0), dtype=dtype)
         v0 = np.ascontiguousarray(np.ravel(v0), dtype=dtype)
         s = x0.shape[0]
+        if kind not in KINDS or method not in METHODS or prec not in PRECS:
+            raise ValueError(f"unknown kind/method/precision {kind!r}/{method!r}/{prec!r}")
+        if v0.shape[0] != s:
+            raise ValueError(f"x0 and v0 must hold the same number of DOFs; got {s} and {v0.shape[0]}")
+        np_want = s if kind == "chain" else s * s
+        if M.size != np_want or K.size != np_want:
+            raise ValueError(f"a {kind} request of s = {s} needs {np_want} values in M and in K; "
+                             f"got {M.size} and {K.size}")
+        if dt.size != 1:
+            raise ValueError("a request takes one step size")
+        if nsteps < 0 or out_stride < 0:
+            raise ValueError("nsteps and out_stride must be >= 0")
         d = Desc(KINDS[kind], METHODS[method], PRECS[prec], s, 1, 1 if kind == "dense" else 0,
                  MEM_HOST, M.ctypes.data, K.ctypes.data, dt.ctypes.data)
         t = ctypes.c_uint64()
