@@ -21,6 +21,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -126,6 +127,21 @@ struct Server {
     void *items = nullptr;       // device copy of work lists
     size_t items_bytes = 0;
 
+    // One iteration's work lists of both precisions: every list is appended
+    // to one host image at its own 256-byte aligned offset, the image goes to
+    // the device in one copy, and each launch reads its list at that offset
+    // once the copy has completed.
+    struct WorkLists {
+        std::vector<unsigned char> image;
+        std::vector<std::function<void(const char *dev, hipStream_t st)>> launches;
+        size_t append(const void *src, size_t bytes) {
+            const size_t off = image.size();
+            image.resize(off + (bytes + 255) / 256 * 256);
+            std::memcpy(image.data() + off, src, bytes);
+            return off;
+        }
+    };
+
     void loop();
     void setup_loop();
     bool setup(Req *r);   // false: the request has been finished (failed) and may be gone
@@ -133,7 +149,8 @@ struct Server {
     void finish(Req *r, osc_status st, const std::string &msg);
     void release_device(Req *r);
     template <typename T>
-    void launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt);
+    void collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, WorkLists &wl, int &next_stream);
+    void launch_lists(WorkLists &wl, std::vector<Req *> &act, int &next_stream);
 };
 
 void Server::release_device(Req *r) {
@@ -208,15 +225,15 @@ bool Server::setup(Req *r) {
     return true;
 }
 
-// Build, upload and launch the work lists of one precision.
+// Build the work lists of one precision into wl (split-path requests, which
+// take no work list, are launched here directly).
 template <typename T>
-void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
+void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, WorkLists &wl, int &next_stream) {
     std::map<std::pair<int, int64_t>, std::vector<ChainItem<T>>> chains;   // (method, layout)
     std::map<std::pair<int, int>, std::vector<DenseItem<T>>> denses;       // (method, smax bucket)
     std::map<std::pair<int, int>, int> dense_smax;
     std::map<std::pair<int, int>, std::vector<DenseMfmaItem>> mfmas;       // (method, padded s)
     const size_t want_elem = sizeof(T);
-    int next_stream = 0;
     for (size_t i = 0; i < act.size(); ++i) {
         Req *r = act[i];
         if (r->elem != want_elem || !r->sys) continue;
@@ -317,72 +334,75 @@ void Server::launch_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt) {
             if (st != OSC_OK) r->status = st;
         }
     }
-    // upload all work lists in one copy, then launch them across the streams
-    size_t bytes = 0;
-    for (auto &g : chains) bytes += (g.second.size() * sizeof(ChainItem<T>) + 255) / 256 * 256;
-    for (auto &g : denses) bytes += (g.second.size() * sizeof(DenseItem<T>) + 255) / 256 * 256;
-    for (auto &g : mfmas) bytes += (g.second.size() * sizeof(DenseMfmaItem) + 255) / 256 * 256;
+    for (auto &g : chains) {
+        const size_t off = wl.append(g.second.data(), g.second.size() * sizeof(ChainItem<T>));
+        const int64_t n = (int64_t)g.second.size();
+        const int method = g.first.first;
+        const ChainConfig cfgc{(int)(g.first.second >> 16), (int)(g.first.second & 0xffff)};
+        wl.launches.push_back([=](const char *dev, hipStream_t st) {
+            (void)chain_launch_items<T>(reinterpret_cast<const ChainItem<T> *>(dev + off), n, method, cfgc, st);
+        });
+    }
+    for (auto &g : denses) {
+        const size_t off = wl.append(g.second.data(), g.second.size() * sizeof(DenseItem<T>));
+        const int64_t n = (int64_t)g.second.size();
+        const int method = g.first.first, smax = dense_smax[g.first];
+        wl.launches.push_back([=](const char *dev, hipStream_t st) {
+            (void)dense_launch_items<T>(reinterpret_cast<const DenseItem<T> *>(dev + off), n, smax, method, st);
+        });
+    }
+    for (auto &g : mfmas) {
+        const size_t off = wl.append(g.second.data(), g.second.size() * sizeof(DenseMfmaItem));
+        const int64_t n = (int64_t)g.second.size();
+        const int method = g.first.first, pad = g.first.second;
+        wl.launches.push_back([=](const char *dev, hipStream_t st) {
+            (void)dense_mfma_launch_items(reinterpret_cast<const DenseMfmaItem *>(dev + off), n, pad, method, st);
+        });
+    }
+}
+
+// Upload every work list of the iteration in one copy and launch the lists
+// across the streams, each after the copy.  The worker drains all streams at
+// the end of every iteration, so neither buffer is in use by an earlier copy
+// or kernel when it is rewritten or replaced here.
+void Server::launch_lists(WorkLists &wl, std::vector<Req *> &act, int &next_stream) {
+    const size_t bytes = wl.image.size();
     if (bytes == 0) return;
     if (bytes > stage_bytes) {
         if (stage) (void)hipHostFree(stage);
         pool_free(items);
-        stage_bytes = bytes * 2;
-        if (hipHostMalloc(&stage, stage_bytes, 0) != hipSuccess) stage = nullptr;
-        items = pool_alloc(stage_bytes);
-        items_bytes = stage_bytes;
+        stage = nullptr;
+        items = nullptr;
+        stage_bytes = items_bytes = 0;
+        if (hipHostMalloc(&stage, bytes * 2, 0) != hipSuccess) stage = nullptr;
+        items = pool_alloc(bytes * 2);
         if (!stage || !items) {
+            if (stage) (void)hipHostFree(stage);
+            pool_free(items);
+            stage = nullptr;
+            items = nullptr;
             for (Req *r : act) r->status = OSC_ENOMEM;
-            stage_bytes = 0;
             return;
         }
+        stage_bytes = items_bytes = bytes * 2;
     }
-    size_t off = 0;
-    std::vector<std::pair<size_t, size_t>> spans;
-    for (auto &g : chains) {
-        std::memcpy(static_cast<char *>(stage) + off, g.second.data(), g.second.size() * sizeof(ChainItem<T>));
-        spans.push_back({off, g.second.size()});
-        off += (g.second.size() * sizeof(ChainItem<T>) + 255) / 256 * 256;
-    }
-    for (auto &g : denses) {
-        std::memcpy(static_cast<char *>(stage) + off, g.second.data(), g.second.size() * sizeof(DenseItem<T>));
-        spans.push_back({off, g.second.size()});
-        off += (g.second.size() * sizeof(DenseItem<T>) + 255) / 256 * 256;
-    }
-    for (auto &g : mfmas) {
-        std::memcpy(static_cast<char *>(stage) + off, g.second.data(), g.second.size() * sizeof(DenseMfmaItem));
-        spans.push_back({off, g.second.size()});
-        off += (g.second.size() * sizeof(DenseMfmaItem) + 255) / 256 * 256;
-    }
+    std::memcpy(stage, wl.image.data(), bytes);
     hipEvent_t ready;
-    (void)hipEventCreateWithFlags(&ready, hipEventDisableTiming);
-    (void)hipMemcpyAsync(items, stage, off, hipMemcpyHostToDevice, streams[0]);
-    (void)hipEventRecord(ready, streams[0]);
-    size_t k = 0;
-    for (auto &g : chains) {
-        hipStream_t st = streams[next_stream];
-        next_stream = (next_stream + 1) % kStreams;
-        (void)hipStreamWaitEvent(st, ready, 0);
-        const ChainConfig cfgc{(int)(g.first.second >> 16), (int)(g.first.second & 0xffff)};
-        (void)chain_launch_items<T>(reinterpret_cast<const ChainItem<T> *>(static_cast<char *>(items) + spans[k].first),
-                                    (int64_t)spans[k].second, g.first.first, cfgc, st);
-        ++k;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) {
+        for (Req *r : act) r->status = OSC_EDEVICE;
+        return;
     }
-    for (auto &g : denses) {
-        hipStream_t st = streams[next_stream];
-        next_stream = (next_stream + 1) % kStreams;
-        (void)hipStreamWaitEvent(st, ready, 0);
-        (void)dense_launch_items<T>(reinterpret_cast<const DenseItem<T> *>(static_cast<char *>(items) + spans[k].first),
-                                    (int64_t)spans[k].second, dense_smax[g.first], g.first.first, st);
-        ++k;
+    if (hipMemcpyAsync(items, stage, bytes, hipMemcpyHostToDevice, streams[0]) != hipSuccess ||
+        hipEventRecord(ready, streams[0]) != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        for (Req *r : act) r->status = OSC_EDEVICE;
+        return;
     }
-    for (auto &g : mfmas) {
+    for (auto &launch : wl.launches) {
         hipStream_t st = streams[next_stream];
         next_stream = (next_stream + 1) % kStreams;
         (void)hipStreamWaitEvent(st, ready, 0);
-        (void)dense_mfma_launch_items(
-            reinterpret_cast<const DenseMfmaItem *>(static_cast<char *>(items) + spans[k].first),
-            (int64_t)spans[k].second, g.first.second, g.first.first, st);
-        ++k;
+        launch(static_cast<const char *>(items), st);
     }
     (void)hipEventDestroy(ready);
 }
@@ -397,8 +417,11 @@ void Server::run_iteration(std::vector<Req *> &act) {
     if (cfg.fake_executor) {
         std::this_thread::sleep_for(std::chrono::duration<double>(std::min(sim, 0.002)));
     } else {
-        launch_groups<float>(act, cnt);
-        launch_groups<double>(act, cnt);
+        WorkLists wl;
+        int next_stream = 0;
+        collect_groups<float>(act, cnt, wl, next_stream);
+        collect_groups<double>(act, cnt, wl, next_stream);
+        launch_lists(wl, act, next_stream);
         for (auto &st : streams) (void)hipStreamSynchronize(st);
     }
     {
