@@ -18,6 +18,8 @@ thread_local std::string g_last_error;
 // for h omega <= 2 sqrt(2) = 2.828, velocity Verlet for h omega < 2.
 constexpr double kRk4Limit = 2.78;
 constexpr double kVerletLimit = 1.99;
+// safety factor on an exact (chains) largest frequency
+constexpr double kStabilityMargin = 1.01;
 
 struct DevBuf {
     void *p = nullptr;
@@ -139,11 +141,26 @@ osc_status create_chain(osc_sys *s, const osc_desc *d) {
     OSC_HIP(hipMemcpyAsync(&host, scratch.p, 16, hipMemcpyDeviceToHost, st));
     OSC_HIP(hipStreamSynchronize(st));
     if (host.bad) return fail(OSC_EINVAL, "chain parameters need m > 0, k >= 0 and finite dt > 0");
-    s->theta_max = host.theta;
     const double lim = s->method == OSC_RK4 ? kRk4Limit : kVerletLimit;
-    if (!(host.theta <= lim))
-        return fail(OSC_EUNSTABLE,
-                    "dt * omega bound " + std::to_string(host.theta) + " exceeds " + std::to_string(lim));
+    double est = host.theta;   // Gershgorin bound: accepted as it is when within the limit
+    if (!(est <= lim)) {
+        // The bound can exceed h omega_max by up to sqrt(2) (unequal masses
+        // across a stiff spring): decide on the exact largest frequency of
+        // each chain instead, with a 1 % margin.
+        DevBuf th;
+        th.p = pool_alloc((size_t)s->batch * sizeof(double));
+        if (!th.p) return fail(OSC_ENOMEM, "device memory exhausted for the stability estimate");
+        if ((r = chain_sturm_theta(s->batch, s->s, s->m, s->k, s->h, static_cast<double *>(th.p), st))) return r;
+        std::vector<double> all((size_t)s->batch);
+        OSC_HIP(hipMemcpyAsync(all.data(), th.p, all.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        OSC_HIP(hipStreamSynchronize(st));
+        est = 0.0;
+        for (double t : all) est = std::max(est, kStabilityMargin * t);
+    }
+    s->theta_max = est;
+    if (!(est <= lim))
+        return fail(OSC_EUNSTABLE, "dt * omega_max (with a 1 % margin) " + std::to_string(est) + " exceeds " +
+                                       std::to_string(lim));
     s->cfg = chain_pick_config(s->s);
     return OSC_OK;
 }
@@ -189,6 +206,44 @@ osc_status plain_chain(osc_sys *s, const void *x0, const void *v0, int64_t nstep
 }
 
 // ------------------------------------------------------------------ dense
+
+// Plain baseline for dense systems: one instance at a time and one time step
+// per launch of the generic (VALU) integrator, the compensated state kept in
+// device memory between launches.
+template <typename T>
+osc_status plain_dense(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, void *xe, void *ve) {
+    const int64_t n = s->s;
+    const size_t ss = (size_t)n * n;
+    if (!s->plain_state) {
+        s->plain_state = pool_alloc(4 * (size_t)s->batch * n * sizeof(T));
+        if (!s->plain_state) return fail(OSC_ENOMEM, "device memory exhausted in osc_integrate_plain");
+    }
+    for (int64_t b = 0; b < s->batch; ++b) {
+        DenseLaunch<T> a{};
+        a.batch = 1;
+        a.s = s->s;
+        a.shared = 1;   // the instance's own operator, addressed directly
+        a.Bh = static_cast<const T *>(s->Bh) + (s->shared ? 0 : b * ss);
+        a.Bl = s->Bl ? static_cast<const T *>(s->Bl) + (s->shared ? 0 : b * ss) : nullptr;
+        a.h = s->h + (s->shared ? 0 : b);
+        a.nonfinite = s->flag;
+        a.x0 = static_cast<const T *>(x0) + b * n;
+        a.v0 = static_cast<const T *>(v0) + b * n;
+        a.state = static_cast<T *>(s->plain_state) + 4 * b * n;
+        a.xe = xe ? static_cast<T *>(xe) + b * n : nullptr;
+        a.ve = ve ? static_cast<T *>(ve) + b * n : nullptr;
+        for (int64_t k = 0; k < nsteps || k == 0; ++k) {
+            a.n0 = k;
+            a.nsteps = nsteps > 0 ? 1 : 0;
+            a.load_mode = k == 0 ? LOAD_USER : LOAD_STATE;
+            a.store_mode = k + 1 >= nsteps ? STORE_USER : STORE_STATE;
+            osc_status r = dense_launch_vec<T>(a, s->method, s->stream);
+            if (r) return r;
+        }
+    }
+    return OSC_OK;
+}
+
 
 template <typename T>
 osc_status create_dense(osc_sys *s, const osc_desc *d) {
@@ -592,7 +647,9 @@ osc_status osc_integrate_plain(osc_sys *s, const void *x0, const void *v0, int64
     if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
     if (s->batch == 0) return OSC_OK;
     if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
-    if (s->kind == OSC_DENSE) return fail(OSC_ENOTSUP, "the plain integrator covers chains only");
+    if (s->kind == OSC_DENSE)
+        return s->prec == OSC_F32 ? plain_dense<float>(s, x0, v0, nsteps, xe, ve)
+                                  : plain_dense<double>(s, x0, v0, nsteps, xe, ve);
     return s->prec == OSC_F32 ? plain_chain<float>(s, x0, v0, nsteps, xe, ve)
                               : plain_chain<double>(s, x0, v0, nsteps, xe, ve);
 }

@@ -110,6 +110,10 @@ template <typename T>
 osc_status chain_prepare(int64_t batch, int s, const double *m, const double *k,
                          const double *dt, T *clh, T *crh, T *cll, T *crl, double *h,
                          double *theta_bound, int *bad_param, hipStream_t st);
+// h omega_max of every chain (exact up to a relative 2^-40, never below it),
+// by Sturm-sequence bisection in FP64; theta: device [batch].
+osc_status chain_sturm_theta(int64_t batch, int s, const double *m, const double *k, const double *dt,
+                             double *theta, hipStream_t st);
 template <typename T>
 osc_status chain_energy(int64_t batch, int s, const double *m, const double *k,
                         const double *h, const T *x, const T *v, double *E, bool shadow,

@@ -66,6 +66,48 @@ __global__ void __launch_bounds__(256) chain_prepare_kernel(int64_t batch, int s
     }
 }
 
+// Exact stability estimate of one chain per thread.  B = h^2 M^-1 K is
+// similar to the symmetric tridiagonal T = M^-1/2 (h^2 K) M^-1/2 with
+//   T_ii = cl_i + cr_i,   T_{i,i+1}^2 = cr_i cl_{i+1},
+// (cl_i = h^2 k_i / m_i, cr_i = h^2 k_{i+1} / m_i), so h^2 omega_max^2 is the
+// largest eigenvalue of T.  Sturm sequence: the number of eigenvalues below
+// t equals the number of negative terms of q_0 = T_00 - t,
+// q_i = T_ii - t - T_{i-1,i}^2 / q_{i-1}.  Bisection on [0, Gershgorin bound]
+// narrows lambda_max to a relative width of 2^-40; the upper end is kept, so
+// the estimate never lies below lambda_max.
+__global__ void __launch_bounds__(256) chain_sturm_kernel(int64_t batch, int s, const double *__restrict__ m,
+                                                          const double *__restrict__ k,
+                                                          const double *__restrict__ dt, double *theta) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const double h = dt[b];
+    const double *mb = m + b * s, *kb = k + b * s;
+    auto cl = [&](int i) { return h * h * kb[i] / mb[i]; };
+    auto cr = [&](int i) { return i + 1 < s ? h * h * kb[i + 1] / mb[i] : 0.0; };
+    double hi = 0.0;
+    for (int i = 0; i < s; ++i) hi = fmax(hi, 2.0 * (cl(i) + cr(i)));
+    // count of eigenvalues below t
+    auto below = [&](double t) {
+        int cnt = 0;
+        double q = 1.0, e2 = 0.0;
+        for (int i = 0; i < s; ++i) {
+            const double d = cl(i) + cr(i);
+            q = d - t - (i > 0 ? e2 / q : 0.0);
+            if (q == 0.0) q = -1e-300;   // t is an eigenvalue of the leading block: count it as passed
+            cnt += q < 0.0;
+            e2 = i + 1 < s ? cr(i) * cl(i + 1) : 0.0;
+        }
+        return cnt;
+    };
+    double lo = 0.0;
+    for (int it = 0; it < 200 && hi - lo > 0x1p-40 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) == s) hi = mid;   // every eigenvalue lies below mid
+        else lo = mid;
+    }
+    theta[b] = sqrt(hi);
+}
+
 // One group of G lanes (power of two <= 64) per instance; FP64 sums reduced
 // across the group with xor shuffles.
 template <typename T, int G>
@@ -132,6 +174,15 @@ osc_status chain_prepare(int64_t batch, int s, const double *m, const double *k,
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
     hipLaunchKernelGGL((chain_prepare_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, batch, s, m, k, dt,
                        clh, crh, cll, crl, h, theta_bound, bad_param);
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
+osc_status chain_sturm_theta(int64_t batch, int s, const double *m, const double *k, const double *dt,
+                             double *theta, hipStream_t st) {
+    if (batch == 0) return OSC_OK;
+    hipLaunchKernelGGL(chain_sturm_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st, batch, s, m,
+                       k, dt, theta);
     OSC_HIP(hipGetLastError());
     return OSC_OK;
 }

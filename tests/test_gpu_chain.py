@@ -166,6 +166,46 @@ def test_create_rejects_bad_parameters():
         assert e.value.status == osc.OSC_EUNSTABLE
 
 
+def _stiff_link_chain(s, theta, heavy=100.0):
+    """Chain whose Gershgorin bound overstates h omega_max by about sqrt(2):
+    light and heavy bodies in turn, a weak wall spring and stiff links."""
+    m = np.where(np.arange(s) % 2 == 0, 1.0, heavy)[None, :]
+    k = np.full((1, s), 1e4)
+    k[0, 0] = 1.0
+    dt = np.array([theta / workloads.chain_omega_max(m, k)[0]])
+    return m, k, dt
+
+
+@pytest.mark.parametrize("s", [2, 301])
+def test_stability_check_uses_exact_frequency(s):
+    """The boundary accepts a step when the exact h omega_max, with a 1 %
+    margin, lies within 2.78 (RK4) or 1.99 (Verlet), even where the
+    Gershgorin bound alone would refuse it, and rejects it otherwise."""
+    from paper_1702_02207_amd import osc
+    for meth, ok_theta, bad_theta in (("rk4", 2.6, 2.76), ("verlet", 1.9, 1.975)):
+        m, k, dt = _stiff_link_chain(s, ok_theta)
+        cl = dt[0] ** 2 * k[0] / m[0]
+        cr = dt[0] ** 2 * np.r_[k[0, 1:], 0.0] / m[0]
+        assert np.sqrt(2 * (cl + cr)).max() > (2.78 if meth == "rk4" else 1.99)   # Gershgorin refuses
+        osc.System("chain", meth, "f32", m, k, dt).create().close()
+        m, k, dt = _stiff_link_chain(s, bad_theta)
+        with pytest.raises(osc.OscError) as e:
+            osc.System("chain", meth, "f32", m, k, dt).create()
+        assert e.value.status == osc.OSC_EUNSTABLE
+
+
+def test_step_near_the_rk4_limit_matches_oracle():
+    """A chain accepted at h omega_max = 2.6 (beyond its Gershgorin bound)
+    integrates like the oracle in FP64."""
+    m, k, dt = _stiff_link_chain(40, 2.6)
+    rng = np.random.default_rng(3)
+    w = workloads.ChainBatch(m, k, dt, rng.normal(size=(1, 40)), rng.normal(size=(1, 40)), 300, 30)
+    xf, vf, _, _ = gpu_chain("rk4", "f64", w)
+    rx, rv, _, _ = oracle_chain("rk4", w)
+    assert oracle.rel_traj_err(xf, rx).max() < 1e-10
+    assert oracle.rel_traj_err(vf, rv).max() < 1e-10
+
+
 def test_empty_batch():
     import torch
     from paper_1702_02207_amd import osc
