@@ -92,6 +92,27 @@ def test_dense_energy(prec):
     np.testing.assert_allclose(E, ref, rtol=1e-12)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("shared", [True, False])
+def test_dense_shadow_energy(prec, shared):
+    """osc_shadow_energy on dense handles (Q = v'Mv + x'Kx - h^2/4 (Kx)'M^-1(Kx))
+    against the oracle's dense invariant, shared and per-instance systems."""
+    import torch
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(11, 37, 5, 10, 0, shared=shared, vscale=1.0)
+    w.dt = w.dt * 150.0            # h omega_max = 1.5: the correction term is a sizeable part of Q
+    sysm = osc.System("dense", "verlet", prec, w.M, w.K, w.dt, shared=shared, batch=5).create()
+    tdt = torch.float32 if prec == "f32" else torch.float64
+    x = torch.as_tensor(w.x0, dtype=tdt, device="cuda")
+    v = torch.as_tensor(w.v0, dtype=tdt, device="cuda")
+    Q = sysm.energy(x, v, shadow=True).cpu().numpy()
+    sysm.sync()
+    sysm.close()
+    ref = oracle.verlet_q_dense(w.M, w.K, w.dt, x.double().cpu().numpy(), v.double().cpu().numpy(),
+                                shared=shared)
+    np.testing.assert_allclose(Q, ref, rtol=1e-11)
+
+
 def test_dense_rejects_non_spd_and_unstable():
     from paper_1702_02207_amd import osc
     M = np.array([[1.0, 2.0], [2.0, 1.0]])
@@ -324,3 +345,34 @@ def test_mfma_misaligned_buffers_give_identical_results(method):
     sysm.close()
     for a, b in zip(ref, got):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+@pytest.mark.parametrize("prec,shared", [("f32", True), ("f64", True), ("f32", False)])
+def test_plain_dense_matches_valu_path_and_oracle(method, prec, shared):
+    """osc_integrate_plain on dense systems (one instance at a time, one step
+    per launch, state in device memory) equals the VALU integrator bitwise
+    (its compensated state survives every launch boundary) and the oracle at
+    the precision's tolerance; zero steps copy the input."""
+    import torch
+    from paper_1702_02207_amd import osc
+    w = _dense_batch(41, 45, 3, 300, 0, shared=shared, vscale=0.3)
+    tdt = torch.float32 if prec == "f32" else torch.float64
+    sysm = osc.System("dense", method, prec, w.M, w.K, w.dt, shared=shared, batch=3).create()
+    sysm.set_config(osc.CFG_DENSE_KERNEL, 1)
+    x0 = torch.as_tensor(w.x0, dtype=tdt, device="cuda")
+    v0 = torch.as_tensor(w.v0, dtype=tdt, device="cuda")
+    _, _, xe, ve = sysm.integrate(x0, v0, w.nsteps, 0)
+    xp, vp = sysm.integrate_plain(x0, v0, w.nsteps)
+    x00, v00 = sysm.integrate_plain(x0, v0, 0)
+    sysm.sync()
+    sysm.close()
+    np.testing.assert_array_equal(xp.cpu().numpy(), xe.cpu().numpy())
+    np.testing.assert_array_equal(vp.cpu().numpy(), ve.cpu().numpy())
+    np.testing.assert_array_equal(x00.cpu().numpy(), x0.cpu().numpy())
+    np.testing.assert_array_equal(v00.cpu().numpy(), v0.cpu().numpy())
+    xi, vi = (f32_inputs(w) if prec == "f32" else (w.x0, w.v0))
+    _, _, rxe, rve = oracle_dense(method, w, x0=xi, v0=vi, stride=0)
+    tol = TOL_F32 if prec == "f32" else TOL_F64
+    assert _err(xp.double().cpu().numpy(), rxe).max() < tol
+    assert _err(vp.double().cpu().numpy(), rve).max() < tol

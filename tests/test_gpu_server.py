@@ -144,3 +144,45 @@ def test_full_stream_sampled_parity():
         ex = oracle.rel_traj_err(res["x_frames"][:, None, :], rx[:, None, :])[0]
         ev = oracle.rel_traj_err(res["v_frames"][:, None, :], rv[:, None, :])[0]
         assert ex < 1e-5 and ev < 1e-5, (r.kind, r.system.s, r.system.nsteps, ex, ev)
+
+
+def test_mixed_precisions_in_one_iteration():
+    """FP32 and FP64 requests of both kinds served together: their work lists
+    share one upload per iteration.  Each result matches the oracle at its
+    precision's tolerance and is bitwise the same as the request served
+    alone."""
+    reqs = _stream(16, seed=23, s_max=300, nsteps=(300, 2000))
+    precs = ["f64" if i % 2 else "f32" for i in range(len(reqs))]
+
+    def submit(srv, r, prec):
+        w = r.system
+        if r.kind == "chain":
+            return srv.submit("chain", "rk4", prec, w.m[0], w.k[0], w.dt, w.x0[0], w.v0[0], w.nsteps,
+                              w.out_stride)
+        return srv.submit("dense", "rk4", prec, w.M, w.K, w.dt, w.x0[0], w.v0[0], w.nsteps, w.out_stride)
+
+    with osc.Server(max_slots=64, chunk_us=300) as srv:
+        tickets = [submit(srv, r, p) for r, p in zip(reqs, precs)]
+        mixed = [srv.wait(t, timeout=120.0) for t in tickets]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert {r.kind for r, p in zip(reqs, precs) if p == "f64"} == {"chain", "dense"}
+    for r, p, res in zip(reqs, precs, mixed):
+        w = r.system
+        x0, v0 = w.x0, w.v0
+        if p == "f32":
+            x0 = x0.astype(np.float32).astype(np.float64)
+            v0 = v0.astype(np.float32).astype(np.float64)
+        if r.kind == "chain":
+            rx, rv, _, _ = oracle.chain("rk4", w.m, w.k, w.dt, x0, v0, w.nsteps, w.out_stride)
+        else:
+            rx, rv, _, _ = oracle.dense("rk4", w.M, w.K, w.dt, x0, v0, w.nsteps, w.out_stride)
+        tol = 1e-10 if p == "f64" else 1e-5
+        ex = oracle.rel_traj_err(res["x_frames"][:, None, :], rx)[0]
+        ev = oracle.rel_traj_err(res["v_frames"][:, None, :], rv)[0]
+        assert ex < tol and ev < tol, (r.kind, p, w.s, ex, ev)
+    for i in range(len(reqs)):
+        with osc.Server(max_slots=4, chunk_us=300) as srv:
+            alone = srv.wait(submit(srv, reqs[i], precs[i]), timeout=120.0)
+        for key in ("x_frames", "v_frames", "x_end", "v_end"):
+            np.testing.assert_array_equal(alone[key], mixed[i][key])
