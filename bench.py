@@ -1,9 +1,11 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the batched oscillator integrator on one MI355X.
 
-Default workload (c2): 2^20 independent two-mass systems (eq. (2)), m1, m2 ~
-LogU[0.5, 5], C1, C2 ~ LogU[1e2, 1e4], x0, v0 ~ N(0, 1), dt = 0.01/omega_max,
-10^4 classic RK4 steps with FP32 state (synthetic, seeded).
+Default workload (c3): 4096 fixed-free spring chains of s = 1024 bodies
+(eq. (2) generalised), masses U[0.5, 2], springs LogU[1e2, 1e4],
+x0 ~ N(0, sigma = 0.1), v0 = 0, dt = 0.01/omega_max per chain, 10^5 classic
+RK4 steps with FP32 state (synthetic, seeded): the largest configuration
+that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c4, c4v, c5).
 
 One timed step is one pass of the whole hot path over the batch, with every
 input already resident in HBM: osc_create from device-resident FP64
@@ -14,12 +16,16 @@ n = nsteps unless stated), osc_energy (FP64 energy of the final state),
 osc_sync and osc_destroy.
 
 Printed JSON line: value = DOF-steps/s = batch * s * nsteps / step time.  Also
-reported: the plain per-instance GPU integrator (one instance at a time, one
-time step per launch) on a sample and the speedup over it, the roofline of the
-dominant kernel (live HIP-event timing of its launch), the FP64 oracle timed
-on the host cores on a bounded sample, and the max relative trajectory error
-of those sampled instances against the oracle.  --workload c5 runs the
-request server instead (p50/p99 latency and DOF-steps/s).
+reported: the plain per-instance GPU integrator (osc_integrate_plain: one
+instance at a time, one time step per launch, full step count) on 64
+instances and the speedup over it; the roofline of the dominant kernel (live
+HIP-event timing of its launch) against the algorithmic flop count of the
+method (classic stage form: RK4 48 flop per DOF-step for chains, 44 for the
+two-mass system; Verlet 10), with the implementation's own count beside it;
+the FP64 oracle timed on the host cores on a bounded sample (instance 0, the
+last instance and seeded others); the relative trajectory error of that
+sample against the oracle; and a served stream (p50/p99 latency, per kind,
+and DOF-steps/s of 200 requests at half the measured saturation rate).
 """
 from __future__ import annotations
 
@@ -36,16 +42,24 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32": 157.3, "fp64": 78.6, "fp16_mfma": 2500.0}   # MI355X published, TFLOP/s
 TOL = {"f32": 1e-5, "f64": 1e-10}
 
-# Algorithmic flops per DOF-step (FMA = 2).  Chains, at the FP32 target
-# precision: RK4 = four B-products (B x with split coefficients 8, three
-# others 4 each), two update polynomials (6 each), two compensated sums (4
-# each) = 40; Verlet leapfrog = split B x 8 + two compensated sums = 16.
-# FP64 chains drop the split and compensation: RK4 28, Verlet 8.  Dense
-# (one operator shared by the batch): the products alone, RK4 4 x 2s, Verlet
-# 1 x 2s (the split FP16 terms the hardware runs are reported separately).
-CHAIN_FLOPS = {("rk4", "f32"): 40, ("verlet", "f32"): 16, ("rk4", "f64"): 28, ("verlet", "f64"): 8}
+# Algorithmic flops per DOF-step (FMA = 2) of the method as the paper states
+# it (classic four-stage RK4 on the first-order system; velocity Verlet):
+# RK4 chains 48 (two-mass system 44), Verlet 10; dense (one operator shared by
+# the batch) the products alone, RK4 4 x 2s, Verlet 1 x 2s.
+ALG_CHAIN_FLOPS = {"rk4": 48, "verlet": 10}
+ALG_CHAIN2_FLOPS = {"rk4": 44, "verlet": 10}
+# The implementation's own count at the FP32 target precision (the exact
+# Taylor form of the RK4 map): four B-products (B x with split coefficients
+# 8, three others 4 each), two update polynomials (6 each) and two
+# compensated sums (4 each) = 40; Verlet leapfrog: split B x 8 + two
+# compensated sums = 16.  FP64 drops the split and compensation: RK4 28,
+# Verlet 8.
+IMPL_CHAIN_FLOPS = {("rk4", "f32"): 40, ("verlet", "f32"): 16, ("rk4", "f64"): 28, ("verlet", "f64"): 8}
 DENSE_PRODUCTS = {"rk4": 4, "verlet": 1}
 DENSE_HW_TERMS = {"rk4": 7, "verlet": 3}     # MFMA products per step with the FP16 splits
+
+# oracle sample sizes (instance 0, the last instance and seeded others)
+CPU_SAMPLE = {"c1": 1, "c2": 65536, "c2v": 65536, "c3": 32, "c3v": 32, "c4": 256, "c4v": 256}
 
 WORKLOADS = {
     "c1": dict(kind="chain", method="rk4", prec="f64",
@@ -117,11 +131,20 @@ def host_threads():
     return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(w, kind, method, prec, sample_n):
-    """Time the FP64 oracle on the first sample_n instances (full step count)."""
+def sample_instances(batch, n, seed=1702022075):
+    """Instance 0, the last instance and n - 2 seeded others in between."""
+    import numpy as np
+    if n >= batch:
+        return np.arange(batch)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mid = rng.choice(np.arange(1, batch - 1), size=max(n - 2, 0), replace=False)
+    return np.unique(np.concatenate([[0, batch - 1], mid]))
+
+
+def cpu_baseline(w, kind, method, prec, idx):
+    """Time the FP64 oracle on the sampled instances (full step count)."""
     import numpy as np
     import oracle
-    idx = np.arange(min(sample_n, w.batch))
     sub = w.subset(idx)
     x0, v0 = sub.x0, sub.v0
     if prec == "f32":
@@ -137,9 +160,9 @@ def cpu_baseline(w, kind, method, prec, sample_n):
     el = time.perf_counter() - t0
     rate = len(idx) * w.s * w.nsteps / el
     return dict(value=rate, unit="DOF-steps/s", cores=min(threads, len(idx)), kind="oracle",
-                sample=f"first {len(idx)} of {w.batch} instances, all {w.nsteps} steps, FP64 C oracle "
-                       f"(OpenMP over instances)",
-                seconds=round(el, 3)), (idx, xf, vf)
+                sample=f"{len(idx)} of {w.batch} instances (instance 0, the last and seeded others), "
+                       f"all {w.nsteps} steps, FP64 C oracle (OpenMP over instances)",
+                seconds=round(el, 3)), (xf, vf)
 
 
 def bench_batched(args, name, spec):
@@ -201,12 +224,15 @@ def bench_batched(args, name, spec):
 
     kavg = float(np.mean(kern_ms)) * 1e-3
     if kind == "chain":
-        fpd = CHAIN_FLOPS[(method, prec)]
+        fpd = (ALG_CHAIN2_FLOPS if w.s == 2 else ALG_CHAIN_FLOPS)[method]
+        impl = IMPL_CHAIN_FLOPS[(method, prec)]
         achieved = fpd * dof_steps / kavg / 1e12
         peak = PEAK["fp32"] if prec == "f32" else PEAK["fp64"]
         roofline = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                         frac=round(achieved / peak, 4), traffic=measured_traffic(name), kernel="chain_kernel",
-                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd)
+                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd,
+                        impl_flops_per_dof_step=impl,
+                        impl_frac=round(impl * dof_steps / kavg / 1e12 / peak, 4))
     else:
         fpd = DENSE_PRODUCTS[method] * 2 * w.s
         achieved = fpd * dof_steps / kavg / 1e12
@@ -228,53 +254,38 @@ def bench_batched(args, name, spec):
     }
 
     if not args.no_plain:
-        pn = min(args.plain_instances if kind == "chain" else max(1, args.plain_instances // 16), w.batch)
-        psteps = args.plain_steps or (w.nsteps if kind == "chain" and w.s <= 8 else min(w.nsteps, 2000))
+        pn = min(args.plain_instances, w.batch)
+        psteps = args.plain_steps or w.nsteps
         sub = w.subset(np.arange(pn))
-        _log(f"[bench] plain integrator: {pn} instances x {psteps} steps")
+        _log(f"[bench] plain integrator: {pn} instances x {psteps} steps, one step per launch")
         if kind == "chain":
             ps = osc.System("chain", method, prec, sub.m, sub.k, sub.dt, stream=stream).create()
-            px0 = torch.as_tensor(sub.x0, dtype=tdt, device=dev)
-            pv0 = torch.as_tensor(sub.v0, dtype=tdt, device=dev)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            pxe, pve = ps.integrate_plain(px0, pv0, psteps)
-            ps.sync()
-            tp = time.perf_counter() - t1
-            ps.close()
         else:
-            # one instance at a time, one step per launch, state in device memory
-            tp = 0.0
-            for i in range(pn):
-                ps = osc.System("dense", method, prec, sub.M, sub.K, sub.dt, shared=True, batch=1,
-                                stream=stream).create()
-                ps.set_config(osc.CFG_DENSE_KERNEL, 1).set_config(osc.CFG_STEPS_PER_LAUNCH, 1)
-                px0 = torch.as_tensor(sub.x0[i:i + 1], dtype=tdt, device=dev)
-                pv0 = torch.as_tensor(sub.v0[i:i + 1], dtype=tdt, device=dev)
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                ps.integrate(px0, pv0, psteps, 0)
-                ps.sync()
-                tp += time.perf_counter() - t1
-                ps.close()
+            ps = osc.System("dense", method, prec, sub.M, sub.K, sub.dt, shared=True, batch=pn,
+                            stream=stream).create()
+        px0 = torch.as_tensor(sub.x0, dtype=tdt, device=dev)
+        pv0 = torch.as_tensor(sub.v0, dtype=tdt, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ps.integrate_plain(px0, pv0, psteps)
+        ps.sync()
+        tp = time.perf_counter() - t1
+        ps.close()
         plain_rate = pn * w.s * psteps / tp
         out["plain"] = {"value": plain_rate, "unit": "DOF-steps/s", "instances": pn, "steps": psteps,
-                        "us_per_launch": tp / (pn * psteps) * 1e6}
+                        "entry_point": "osc_integrate_plain",
+                        "us_per_launch": tp / (pn * max(psteps, 1)) * 1e6}
         out["speedup_vs_plain"] = value / plain_rate
 
     if not args.no_cpu_baseline:
-        if args.cpu_sample:
-            sample = args.cpu_sample
-        elif kind == "chain":
-            sample = 65536 if w.s <= 8 else 16
-        else:
-            sample = 8
-        _log(f"[bench] oracle on {min(sample, w.batch)} instances")
-        cb, (idx, rxf, rvf) = cpu_baseline(w, kind, method, prec, sample)
+        n = args.cpu_sample or CPU_SAMPLE.get(name, 16)
+        idx = sample_instances(w.batch, n)
+        _log(f"[bench] oracle on {len(idx)} instances")
+        cb, (rxf, rvf) = cpu_baseline(w, kind, method, prec, idx)
         out["cpu_baseline"] = cb
         import oracle
-        gx = xf[:, :len(idx)].double().cpu().numpy()
-        gv = vf[:, :len(idx)].double().cpu().numpy()
+        gx = xf[:, torch.as_tensor(idx, device=dev)].double().cpu().numpy()
+        gv = vf[:, torch.as_tensor(idx, device=dev)].double().cpu().numpy()
         ex = oracle.rel_traj_err(gx, rxf)
         ev = oracle.rel_traj_err(gv, rvf)
         out["error"] = {"max_rel_err_x": float(ex.max()), "max_rel_err_v": float(ev.max()),
@@ -286,35 +297,56 @@ def bench_batched(args, name, spec):
     return out
 
 
-def bench_serve(args, spec):
+def serve_pass(args, method="rk4", prec="f32"):
+    """The served stream: a burst of every request at once measures the
+    saturation rate, then Poisson arrivals at args.load times that rate."""
     import numpy as np
     from paper_1702_02207_amd import serve, workloads
-    _log(f"[bench] generating {args.requests} requests")
+    _log(f"[bench] serving: generating {args.requests} requests")
     reqs = workloads.c5_request_stream(n_requests=args.requests, qps=1.0)
     work = sum(r.system.s * r.system.nsteps for r in reqs)
-    _log("[bench] burst (saturation)")
-    sat = serve.run_stream(reqs, None, method=spec["method"], prec=spec["prec"],
-                           hbm_budget=args.hbm_budget)
+    _log("[bench] serving: burst (saturation)")
+    sat = serve.run_stream(reqs, None, method=method, prec=prec, hbm_budget=args.hbm_budget)
     sat_qps = len(reqs) / sat["makespan_s"]
     qps = args.qps or args.load * sat_qps
-    _log(f"[bench] Poisson arrivals at {qps:.2f} requests/s")
+    _log(f"[bench] serving: Poisson arrivals at {qps:.2f} requests/s")
     arr = serve.poisson_arrivals(len(reqs), qps, seed=1702022074)
-    run = serve.run_stream(reqs, arr, method=spec["method"], prec=spec["prec"], hbm_budget=args.hbm_budget)
-    out = {
-        "metric": "DOF-steps/sec batched vs plain at stated err; p50/p99 solve latency",
-        "value": run["dof_steps_per_s"], "unit": "DOF-steps/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": run["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": spec["prec"], "data": "synthetic",
-        "config": {"workload": spec["desc"], "requests": len(reqs), "qps": qps,
-                   "hbm_budget": args.hbm_budget, "total_dof_steps": int(work)},
-        "serving": {"p50_latency_s": run["p50_latency_s"], "p99_latency_s": run["p99_latency_s"],
-                    "mean_latency_s": run["mean_latency_s"], "failed": run["failed"],
-                    "hbm_peak_bytes": run["hbm_peak_bytes"], "iterations": run["iterations"],
-                    "worker_setup_s": run["worker_setup_s"], "worker_iterate_s": run["worker_iterate_s"],
-                    "saturation": {"requests_per_s": sat_qps, "dof_steps_per_s": sat["dof_steps_per_s"],
-                                   "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"]}},
+    run = serve.run_stream(reqs, arr, method=method, prec=prec, hbm_budget=args.hbm_budget)
+
+    def per_kind(res):
+        d = {}
+        for kind in ("chain", "dense"):
+            lat = np.array([x["latency_s"] for r, x in zip(reqs, res["results"]) if x is not None and r.kind == kind])
+            if lat.size:
+                d[kind] = {"requests": int(lat.size), "p50_latency_s": float(np.percentile(lat, 50)),
+                           "p99_latency_s": float(np.percentile(lat, 99))}
+        return d
+
+    return {
+        "workload": WORKLOADS["c5"]["desc"], "requests": len(reqs), "qps": qps, "load": args.load,
+        "hbm_budget": args.hbm_budget, "total_dof_steps": int(work),
+        "p50_latency_s": run["p50_latency_s"], "p99_latency_s": run["p99_latency_s"],
+        "mean_latency_s": run["mean_latency_s"], "dof_steps_per_s": run["dof_steps_per_s"],
+        "makespan_s": run["makespan_s"], "per_kind": per_kind(run), "failed": run["failed"],
+        "hbm_peak_bytes": run["hbm_peak_bytes"], "iterations": run["iterations"],
+        "worker_setup_s": run["worker_setup_s"], "worker_iterate_s": run["worker_iterate_s"],
+        "saturation": {"requests_per_s": sat_qps, "dof_steps_per_s": sat["dof_steps_per_s"],
+                       "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"],
+                       "per_kind": per_kind(sat)},
     }
-    return out
+
+
+def bench_serve(args, spec):
+    sv = serve_pass(args, spec["method"], spec["prec"])
+    return {
+        "metric": "DOF-steps/sec batched vs plain at stated err; p50/p99 solve latency",
+        "value": sv["dof_steps_per_s"], "unit": "DOF-steps/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": sv["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": spec["prec"], "data": "synthetic",
+        "config": {"workload": spec["desc"], "requests": sv["requests"], "qps": sv["qps"],
+                   "hbm_budget": args.hbm_budget, "total_dof_steps": sv["total_dof_steps"]},
+        "serving": sv,
+    }
 
 
 def main():
@@ -322,10 +354,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--plain-instances", type=int, default=64)
     ap.add_argument("--plain-steps", type=int, default=0, help="0 = workload default")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="0 = workload default")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="0 = workload default (CPU_SAMPLE)")
+    ap.add_argument("--no-serve", action="store_true", help="leave the served-stream pass out of the line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the stream")
@@ -353,7 +386,14 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4}))
         return
     spec = WORKLOADS[args.workload]
-    out = bench_serve(args, spec) if spec["kind"] == "serve" else bench_batched(args, args.workload, spec)
+    if spec["kind"] == "serve":
+        out = bench_serve(args, spec)
+    else:
+        out = bench_batched(args, args.workload, spec)
+        if not args.no_serve:
+            out["serving"] = serve_pass(args)
+    for r in (out.get("serving") or {}), (out.get("serving") or {}).get("saturation", {}):
+        r.pop("results", None)
     print(json.dumps(out), flush=True)
 
 
