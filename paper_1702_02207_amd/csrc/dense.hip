@@ -323,8 +323,8 @@ __device__ __forceinline__ void dense_vec_run(const DenseLaunch<T> &a, const int
                         p2 = fmat(bh, su[j], p2);
                         q2 = fmat(bh, sv[j], q2);
                     }
-                    const T yx = fmat(T(1.0 / 24.0), p2, fmat(T(-1.0 / 6.0), Q[r], fmat(T(-0.5), P[r], w[r])));
-                    const T yw = fmat(T(1.0 / 24.0), q2, fmat(T(1.0 / 6.0), p2, fmat(T(-0.5), Q[r], -P[r])));
+                    T yx, yw;
+                    rk4_increments(w[r], P[r], Q[r], p2, q2, yx, yw);
                     comp_add(x[r], xl[r], yx);
                     comp_add(w[r], wl[r], yw);
                 }

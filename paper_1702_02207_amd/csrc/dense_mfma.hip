@@ -283,9 +283,12 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
         }
     };
 
-    // RK4 coefficients in scaled units (ib = 1 / beta, a power of two)
-    const float c1 = -0.5f * ib, c2 = -ib / 6.0f, c3 = ib * ib / 24.0f;
-    const float d1 = -ib, d2 = -0.5f * ib, d3 = ib * ib / 6.0f, d4 = ib * ib / 24.0f;
+    // RK4 increments (the products are B^ u = beta B u, ib = 1 / beta, a
+    // power of two), each summed from its smallest term up and rounded once
+    // at the scale of its dominant term:
+    //   dx = w - (ib/2) (P + Q/3 - ib P2/12)
+    //   dw = -ib (P + (Q - ib P2/3 - ib Q2/12) / 2)
+    const float e1 = -ib / 12.0f, e2 = -ib / 3.0f, e3 = -0.5f * ib;
 
     int64_t n = a.n0;
     const int64_t nend = a.n0 + a.nsteps;
@@ -299,29 +302,23 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
         }
         for (int64_t it = n; it < stop; ++it) {
             if constexpr (METHOD == OSC_RK4) {
-                // each product is folded into dx, dw and written out as the next
-                // operand as soon as it is formed, so only one is live at a time
-                float dx[RT][4], dw[RT][4], T[RT][4];
+                // each product is folded into the partial sums and written out
+                // as the next operand as soon as it is formed; P, sx and sw
+                // stay live until the increments are complete
+                float pk[RT][4], sx[RT][4], sw[RT][4], T[RT][4];
                 __syncthreads();
                 put(bufA, x, true);
                 put(bufB, w, false);
                 __syncthreads();
-                prod3(bufA, T);   // P = B^ x
-#pragma unroll
-                for (int t = 0; t < RT; ++t)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        dx[t][r] = __builtin_fmaf(c1, T[t][r], w[t][r]);
-                        dw[t][r] = d1 * T[t][r];
-                    }
-                put(bufC, T, false);
+                prod3(bufA, pk);   // P = B^ x
+                put(bufC, pk, false);
                 prod2(bufB, T);   // Q = B^ w
 #pragma unroll
                 for (int t = 0; t < RT; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        dx[t][r] = __builtin_fmaf(c2, T[t][r], dx[t][r]);
-                        dw[t][r] = __builtin_fmaf(d2, T[t][r], dw[t][r]);
+                        sx[t][r] = __builtin_fmaf(1.0f / 3.0f, T[t][r], pk[t][r]);
+                        sw[t][r] = T[t][r];
                     }
                 put(bufD, T, false);
                 __syncthreads();
@@ -330,17 +327,17 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
                 for (int t = 0; t < RT; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        dx[t][r] = __builtin_fmaf(c3, T[t][r], dx[t][r]);
-                        dw[t][r] = __builtin_fmaf(d3, T[t][r], dw[t][r]);
+                        sx[t][r] = __builtin_fmaf(e1, T[t][r], sx[t][r]);
+                        sw[t][r] = __builtin_fmaf(e2, T[t][r], sw[t][r]);
+                        comp_add(x[t][r], xl[t][r][lane], __builtin_fmaf(e3, sx[t][r], w[t][r]));
                     }
                 prod1(bufD, T);   // Q2 = B^ Q
 #pragma unroll
                 for (int t = 0; t < RT; ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        dw[t][r] = __builtin_fmaf(d4, T[t][r], dw[t][r]);
-                        comp_add(x[t][r], xl[t][r][lane], dx[t][r]);
-                        comp_add(w[t][r], wl[t][r][lane], dw[t][r]);
+                        sw[t][r] = __builtin_fmaf(e1, T[t][r], sw[t][r]);
+                        comp_add(w[t][r], wl[t][r][lane], -ib * __builtin_fmaf(0.5f, sw[t][r], pk[t][r]));
                     }
             } else {
 #pragma unroll

@@ -251,8 +251,8 @@ __global__ void __launch_bounds__(kRowThreads) split_update(DenseSplitLaunch<T> 
     const T P = part_sum(a, kP, b, row), Q = part_sum(a, kQ, b, row);
     const T P2 = part_sum(a, kP2, b, row), Q2 = part_sum(a, kQ2, b, row);
     T x = a.state[i], xl = a.state[plane + i], w = a.state[2 * plane + i], wl = a.state[3 * plane + i];
-    const T yx = fmat(T(1.0 / 24.0), P2, fmat(T(-1.0 / 6.0), Q, fmat(T(-0.5), P, w)));
-    const T yw = fmat(T(1.0 / 24.0), Q2, fmat(T(1.0 / 6.0), P2, fmat(T(-0.5), Q, -P)));
+    T yx, yw;
+    rk4_increments(w, P, Q, P2, Q2, yx, yw);
     comp_add(x, xl, yx);
     comp_add(w, wl, yw);
     a.state[i] = x;
