@@ -106,9 +106,14 @@ typedef struct osc_sys osc_sys;
  * dt^2; for dense systems, A = M^-1 K by FP64 Cholesky and its scaled split
  * operands.  Checks positive definiteness (OSC_ENOTSPD) and stability: the
  * step is rejected (OSC_EUNSTABLE) when dt * omega_bound exceeds 2.78 for
- * RK4 (the imaginary-axis limit is 2*sqrt(2)) or 1.99 for Verlet (limit 2),
- * with omega_bound a Gershgorin bound (chains) or a power-iteration estimate
- * with a 2 % margin (dense).  Blocks until the preparation has finished.
+ * RK4 (the imaginary-axis limit is 2*sqrt(2)) or 1.99 for Verlet (limit 2).
+ * omega_bound is first a cheap upper bound (Gershgorin for chains, the
+ * largest absolute row sum of A for dense systems); when that exceeds the
+ * limit it is replaced by an estimate of the largest frequency itself: for
+ * chains the exact value (Sturm-sequence bisection on the symmetric
+ * tridiagonal M^-1/2 K M^-1/2, FP64) with a 1 % margin, for dense systems
+ * power iteration (which approaches it from below) with a 2 % margin.
+ * Blocks until the preparation has finished.
  * stream: hipStream_t or NULL.  *out receives a new handle on success.
  */
 osc_status osc_create(const osc_desc *desc, void *stream, osc_sys **out);
@@ -125,6 +130,35 @@ osc_status osc_create(const osc_desc *desc, void *stream, osc_sys **out);
 osc_status osc_integrate(osc_sys *sys, const void *x0, const void *v0, int64_t nsteps,
                          int64_t out_stride, void *x_frames, void *v_frames, void *x_end,
                          void *v_end);
+
+/*
+ * osc_integrate_static -- osc_integrate for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, and bit for bit the same results,
+ * as osc_integrate with the handle's configuration.  Every device buffer the
+ * run needs beyond the caller's inputs and outputs (the compensated state
+ * carried between launches when OSC_CFG_STEPS_PER_LAUNCH splits the run; the
+ * split dense path's state, carried product, partial sums and step counter)
+ * is taken from one scratch array of OSC_STATIC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine) and
+ * captures no graph: its kernels are enqueued directly on the handle's stream,
+ * so that a caller may capture them.  The first call on a device looks up the
+ * array's address there (hipGetSymbolAddress).  Nothing in the scratch needs
+ * to start at zero: every value is written before it is read.
+ * Errors: OSC_ENOMEM (with the size needed) when the run needs more scratch
+ * than the maximum (a chunked run needs 4 * batch * s elements plus one float
+ * per instance; the split path that plus (1 + 4 * column groups) * batch * s
+ * elements); OSC_ENOTSUP for dense systems with per-instance operators on the
+ * matrix-core path (their work list is uploaded per call).
+ * Every call on one device shares that device's scratch: calls that overlap
+ * in time on one device (on different streams or host threads) race, and the
+ * caller must order them.
+ */
+#define OSC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+osc_status osc_integrate_static(osc_sys *sys, const void *x0, const void *v0, int64_t nsteps,
+                                int64_t out_stride, void *x_frames, void *v_frames, void *x_end,
+                                void *v_end);
 
 /*
  * osc_integrate_plain -- the same result as osc_integrate with no frames,

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -9,10 +10,41 @@
 
 #include "osc_internal.h"
 
+// Device scratch of the allocation-free entry point (osc_integrate_static):
+// each device that runs the library holds its own copy from the library's
+// load on that device until the process ends.  In host code `scratch` names
+// a host-side stand-in, never the device memory: kernels and copies take the
+// per-device address that static_scratch() obtains from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[OSC_STATIC_SCRATCH_BYTES];
+
 namespace osc {
 
 namespace {
 thread_local std::string g_last_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on `device`, looked up once per device with that
+// device current (the caller's current device is restored).
+osc_status static_scratch(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(OSC_EDEVICE, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        OSC_HIP(hipGetDevice(&cur));
+        if (cur != device) OSC_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(OSC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return OSC_OK;
+}
 
 // Stability limits on the imaginary axis with a small margin: RK4 is stable
 // for h omega <= 2 sqrt(2) = 2.828, velocity Verlet for h omega < 2.
@@ -49,8 +81,15 @@ size_t elem(const osc_sys *s) { return s->prec == OSC_F64 ? sizeof(double) : siz
 
 // State planes [4][batch][s] followed by one float per instance (the MFMA
 // path's operand scale).
+size_t state_bytes(const osc_sys *s) { return 4 * (size_t)s->batch * s->s * elem(s) + (size_t)s->batch * sizeof(float); }
+
+void *state_buf(const osc_sys *s) { return s->static_call ? s->scratch_state : s->state; }
+void *split_buf(const osc_sys *s) { return s->static_call ? s->scratch_split : s->split_scratch; }
+
 osc_status ensure_state(osc_sys *s) {
-    const size_t need = 4 * (size_t)s->batch * s->s * elem(s) + (size_t)s->batch * sizeof(float);
+    if (s->static_call)
+        return s->scratch_state ? OSC_OK : fail(OSC_EINVAL, "internal: no static scratch for the chunked state");
+    const size_t need = state_bytes(s);
     if (s->state && s->state_bytes >= need) return OSC_OK;
     pool_free(s->state);
     s->state = pool_alloc(need);
@@ -62,7 +101,7 @@ osc_status ensure_state(osc_sys *s) {
 template <typename L>
 void set_sigma(L &, osc_sys *) {}
 void set_sigma(DenseMfmaLaunch &a, osc_sys *s) {
-    a.sigma = reinterpret_cast<float *>(static_cast<char *>(s->state) + 4 * (size_t)s->batch * s->s * sizeof(float));
+    a.sigma = reinterpret_cast<float *>(static_cast<char *>(state_buf(s)) + 4 * (size_t)s->batch * s->s * sizeof(float));
 }
 
 // Advance [0, nsteps) in launches of at most steps_per_launch steps, passing
@@ -85,7 +124,7 @@ osc_status run_chunks(osc_sys *s, L base, int64_t nsteps, F &&launch) {
         a.nsteps = chunk < nsteps - n0 ? chunk : nsteps - n0;
         a.load_mode = n0 == 0 ? LOAD_USER : LOAD_STATE;
         a.store_mode = n0 + a.nsteps == nsteps ? STORE_USER : STORE_STATE;
-        a.state = static_cast<decltype(a.state)>(s->state);
+        a.state = static_cast<decltype(a.state)>(state_buf(s));
         set_sigma(a, s);
         if ((r = launch(a))) return r;
     }
@@ -362,15 +401,17 @@ osc_status integrate_split(osc_sys *s, const void *x0, const void *v0, int64_t n
     a.out_stride = out_stride;
     a.xf = static_cast<T *>(xf);
     a.vf = static_cast<T *>(vf);
-    // the graph replays phase kernels only: key on what they read
-    static_assert(sizeof(DenseSplitLaunch<T>) <= sizeof(s->split_key), "graph key too small");
-    unsigned char key[sizeof(s->split_key)] = {};
-    std::memcpy(key, &a, sizeof(a));
-    if (std::memcmp(key, s->split_key, sizeof(key)) != 0 && s->split_graph) {
-        (void)hipGraphExecDestroy(s->split_graph);
-        s->split_graph = nullptr;
+    if (!s->static_call) {
+        // the graph replays phase kernels only: key on what they read
+        static_assert(sizeof(DenseSplitLaunch<T>) <= sizeof(s->split_key), "graph key too small");
+        unsigned char key[sizeof(s->split_key)] = {};
+        std::memcpy(key, &a, sizeof(a));
+        if (std::memcmp(key, s->split_key, sizeof(key)) != 0 && s->split_graph) {
+            (void)hipGraphExecDestroy(s->split_graph);
+            s->split_graph = nullptr;
+        }
+        std::memcpy(s->split_key, key, sizeof(key));
     }
-    std::memcpy(s->split_key, key, sizeof(key));
     a.x0 = static_cast<const T *>(x0);
     a.v0 = static_cast<const T *>(v0);
     a.xe = static_cast<T *>(xe);
@@ -379,7 +420,10 @@ osc_status integrate_split(osc_sys *s, const void *x0, const void *v0, int64_t n
     a.nsteps = nsteps;
     a.load_mode = LOAD_USER;
     a.store_mode = STORE_USER;
-    const int64_t gsteps = s->stream ? s->graph_steps : 0;   // no capture on the null stream
+    // no capture on the null stream, nor in an allocation-free call (whose
+    // launches a caller may itself be capturing)
+    const int64_t gsteps = (s->stream && !s->static_call) ? s->graph_steps : 0;
+    if (s->static_call) return dense_split_run<T>(a, s->method, s->stream, nullptr, nullptr, 0);
     return dense_split_run<T>(a, s->method, s->stream, &s->split_graph, &s->split_graph_len, gsteps);
 }
 
@@ -497,6 +541,8 @@ bool dense_uses_split(const osc_sys *s) { return use_split(s); }
 osc_status sys_ensure_state(osc_sys *s) { return ensure_state(s); }
 
 osc_status sys_ensure_split_scratch(osc_sys *s) {
+    if (s->static_call)
+        return s->scratch_split ? OSC_OK : fail(OSC_EINVAL, "internal: no static scratch for the split path");
     const size_t e = s->prec == OSC_F64 ? 8 : 4;
     if (!s->split_scratch) {
         s->split_scratch = pool_alloc(dense_split_scratch_elems(s->s, s->batch) * e + 64);
@@ -515,8 +561,8 @@ void split_launch_base(osc_sys *s, DenseSplitLaunch<T> &a) {
     a.Bh = static_cast<const T *>(s->Bh);
     a.Bl = static_cast<const T *>(s->Bl);
     a.h = s->h;
-    a.state = static_cast<T *>(s->state);
-    a.P = static_cast<T *>(s->split_scratch);
+    a.state = static_cast<T *>(state_buf(s));
+    a.P = static_cast<T *>(split_buf(s));
     a.part = a.P + n;
     a.counter = reinterpret_cast<int64_t *>(a.part + 4 * (size_t)a.groups * n);
     a.nonfinite = s->flag;
@@ -625,20 +671,65 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
     return fail(OSC_EINVAL, "unknown configuration key");
 }
 
-osc_status osc_integrate(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride, void *xf,
-                         void *vf, void *xe, void *ve) {
-    g_last_error.clear();
+static osc_status integrate_checks(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                                   const void *xf, const void *vf) {
     if (!s) return fail(OSC_EINVAL, "handle is NULL");
     if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
     if (out_stride < 0) return fail(OSC_EINVAL, "out_stride must be >= 0");
     if (out_stride == 0 && (xf || vf)) return fail(OSC_EINVAL, "frames requested with out_stride == 0");
-    if (s->batch == 0) return OSC_OK;
-    if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
+    if (s->batch > 0 && (!x0 || !v0)) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
+    return OSC_OK;
+}
+
+static osc_status integrate_any(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                                void *xf, void *vf, void *xe, void *ve) {
     if (s->kind == OSC_DENSE)
         return s->prec == OSC_F32 ? integrate_dense<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                                   : integrate_dense<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
     return s->prec == OSC_F32 ? integrate_chain<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                               : integrate_chain<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
+}
+
+osc_status osc_integrate(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride, void *xf,
+                         void *vf, void *xe, void *ve) {
+    g_last_error.clear();
+    osc_status r = integrate_checks(s, x0, v0, nsteps, out_stride, xf, vf);
+    if (r || s->batch == 0) return r;
+    return integrate_any(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
+}
+
+osc_status osc_integrate_static(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                                void *xf, void *vf, void *xe, void *ve) {
+    g_last_error.clear();
+    osc_status r = integrate_checks(s, x0, v0, nsteps, out_stride, xf, vf);
+    if (r || s->batch == 0) return r;
+    // device memory the run needs beyond its inputs and outputs
+    size_t need_state = 0, need_split = 0;
+    if (s->kind == OSC_DENSE && use_mfma(s) && !s->shared)
+        return fail(OSC_ENOTSUP, "osc_integrate_static: per-instance operators on the matrix cores take a work "
+                                 "list built per call; use osc_integrate");
+    if (s->kind == OSC_DENSE && !use_mfma(s) && use_split(s)) {
+        need_state = state_bytes(s);
+        need_split = dense_split_scratch_elems(s->s, s->batch) * elem(s) + 64;
+    } else if (s->steps_per_launch > 0 && nsteps > s->steps_per_launch) {
+        need_state = state_bytes(s);
+    }
+    const size_t off = (need_state + 255) / 256 * 256;
+    const size_t need = off + need_split;
+    if (need > OSC_STATIC_SCRATCH_BYTES)
+        return fail(OSC_ENOMEM, "osc_integrate_static: the run needs " + std::to_string(need) +
+                                    " bytes of device scratch; the maximum is " +
+                                    std::to_string((size_t)OSC_STATIC_SCRATCH_BYTES) +
+                                    " (fewer instances per call, or osc_integrate)");
+    void *base = nullptr;
+    if (need > 0 && (r = static_scratch(s->device, &base))) return r;
+    s->static_call = true;
+    s->scratch_state = need_state ? base : nullptr;
+    s->scratch_split = need_split ? static_cast<char *>(base) + off : nullptr;
+    r = integrate_any(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
+    s->static_call = false;
+    s->scratch_state = s->scratch_split = nullptr;
+    return r;
 }
 
 osc_status osc_integrate_plain(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, void *xe, void *ve) {

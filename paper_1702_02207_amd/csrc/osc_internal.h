@@ -300,4 +300,11 @@ struct osc_sys {
     void *plain_state = nullptr;         // state planes of the plain baseline
     double theta_max = 0.0;              // largest dt * omega bound over the batch
     osc::ChainConfig cfg{1, 1};
+    // osc_integrate_static: for the length of one call the chunked-run state
+    // and the split path's buffers are parts of the library's static device
+    // scratch instead of the handle's own (allocated on demand), and no graph
+    // is captured
+    bool static_call = false;
+    void *scratch_state = nullptr;
+    void *scratch_split = nullptr;
 };

@@ -73,6 +73,7 @@ def load():
     sig = {
         "osc_create": (i32, [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]),
         "osc_integrate": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp]),
+        "osc_integrate_static": (i32, [vp, vp, vp, i64, i64, vp, vp, vp, vp]),
         "osc_integrate_plain": (i32, [vp, vp, vp, i64, vp, vp]),
         "osc_energy": (i32, [vp, vp, vp, vp]),
         "osc_shadow_energy": (i32, [vp, vp, vp, vp]),
@@ -210,9 +211,11 @@ class System:
         return self._tensor(t, (self.batch, self.s), self.dtype, what)
 
     def integrate(self, x0, v0, nsteps: int, out_stride: int = 0, frames: bool = True,
-                  out=None):
+                  out=None, static: bool = False):
         """Returns (x_frames, v_frames, x_end, v_end) as new device tensors
-        (frames None when out_stride == 0 or frames is False)."""
+        (frames None when out_stride == 0 or frames is False).  static: call
+        osc_integrate_static (no device allocation inside the library; pass
+        ``out`` to allocate nothing at all)."""
         import torch
         x0, v0 = self._state(x0, "x0"), self._state(v0, "v0")
         if nsteps < 0 or out_stride < 0:
@@ -235,9 +238,9 @@ class System:
             for t, what in ((xe, "x_end"), (ve, "v_end")):
                 if t is not None:
                     self._state(t, what)
-        _check(load().osc_integrate(self.handle, _dptr(x0), _dptr(v0), int(nsteps),
-                                    int(out_stride) if nf else 0, _dptr(xf), _dptr(vf),
-                                    _dptr(xe), _dptr(ve)))
+        entry = load().osc_integrate_static if static else load().osc_integrate
+        _check(entry(self.handle, _dptr(x0), _dptr(v0), int(nsteps), int(out_stride) if nf else 0,
+                     _dptr(xf), _dptr(vf), _dptr(xe), _dptr(ve)))
         return xf, vf, xe, ve
 
     def integrate_plain(self, x0, v0, nsteps: int):
