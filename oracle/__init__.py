@@ -52,7 +52,8 @@ def _load():
     lib.oracle_energy_dense.argtypes = [i64, i32, i32, d, d, d, d, d]
     lib.oracle_verlet_q_chain.argtypes = [i64, i32, d, d, d, d, d, d]
     lib.oracle_verlet_q_dense.argtypes = [i64, i32, i32, d, d, d, d, d, d]
-    for f in ("oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
+    lib.oracle_propagator.argtypes = [i32, i32, i32, d, d, ctypes.c_double, i64, d]
+    for f in ("oracle_propagator", "oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
               "oracle_energy_dense", "oracle_verlet_q_chain", "oracle_verlet_q_dense"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -164,6 +165,20 @@ def verlet_q_dense(M, K, dt, x, v, shared=True):
     _check(lib.oracle_verlet_q_dense(batch, s, 1 if shared else 0, _p(M), _p(K), _p(dt), _p(x), _p(v),
                                      _p(Q)), "verlet_q_dense")
     return Q
+
+
+def propagator(method, kind, a, b, dt, k=1):
+    """The matrix P_k of k steps of the scheme on y = (x, v) (positions
+    first): y_{n+k} = P_k y_n, [2s, 2s].  kind "chain": a = m, b = k ([s]);
+    "dense": a = M, b = K ([s, s]).  Column j is k oracle steps started from
+    the j-th unit vector."""
+    lib = _load()
+    a, b = _f64(a), _f64(b)
+    s = a.shape[0]
+    P = np.empty((2 * s, 2 * s))
+    _check(lib.oracle_propagator(_METHODS[method], {"chain": 0, "dense": 1}[kind], s, _p(a), _p(b),
+                                 float(dt), int(k), _p(P)), "oracle_propagator")
+    return P
 
 
 def rel_traj_err(got, ref):

@@ -396,3 +396,53 @@ int oracle_verlet_q_dense(int64_t batch, int s, int shared, const double *M, con
     free(ax);
     return st;
 }
+
+/* ----------------------------------------------------------------------- */
+/* the scheme as a matrix                                                    */
+/* ----------------------------------------------------------------------- */
+
+/* For eq. (1) the first-order system of section 3 is y' = L y with the
+ * constant matrix L = [[0, I], [-A, 0]], y = (x, v), and both schemes map y
+ * linearly: k steps are one matrix P_k, y_{n+k} = P_k y_n.  Column j of P_k
+ * is the state after k steps started from the j-th unit vector of R^2s; that
+ * is how it is formed here, with the integrator above.
+ * kind 0: chain (a = m, b = k, each [s]); kind 1: dense (a = M, b = K, each
+ * [s][s], A = M^-1 K by Cholesky).  P: [2s][2s] row-major, positions first. */
+int oracle_propagator(int method, int kind, int s, const double *a, const double *b, double dt,
+                      int64_t k, double *P) {
+    if ((method != ORC_RK4 && method != ORC_VERLET) || (kind != 0 && kind != 1) || s < 1 || k < 0 ||
+        !a || !b || !P || !(dt > 0.0))
+        return ORC_EINVAL;
+    const int n = 2 * s;
+    double *A = NULL;
+    if (kind == 1) {
+        A = (double *)malloc(sizeof(double) * (size_t)s * s);
+        if (!A) return ORC_ENOMEM;
+        int st = oracle_form_a(s, a, b, A);
+        if (st) { free(A); return st; }
+    }
+    rhs_t r = {kind, s, kind == 0 ? a : NULL, kind == 0 ? b : NULL, A};
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * ORC_WORK_PER_DOF * (size_t)s);
+        double *y0 = (double *)malloc(sizeof(double) * n);
+        double *ye = (double *)malloc(sizeof(double) * n);
+        if (!work || !y0 || !ye) {
+#pragma omp atomic write
+            fail = ORC_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int j = 0; j < n; ++j) {
+                for (int i = 0; i < n; ++i) y0[i] = (i == j) ? 1.0 : 0.0;
+                integrate_one(&r, method, dt, y0, y0 + s, k, 0, 1, 0, NULL, NULL, ye, ye + s, work);
+                for (int i = 0; i < n; ++i) P[(size_t)i * n + j] = ye[i];
+            }
+        }
+        free(work);
+        free(y0);
+        free(ye);
+    }
+    free(A);
+    return fail;
+}

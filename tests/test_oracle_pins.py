@@ -459,3 +459,116 @@ def test_pins_catch_planted_oracle_mistakes(orig, mut, tmp_path):
         err = max(oracle.rel_traj_err(xe, xr)[0], oracle.rel_traj_err(ve, vr)[0])
         bad = bad or not (err < 1e-11)
     assert bad, "planted mistake not detected"
+
+
+# ------------------------------------------------ the scheme as a matrix -----
+
+def _first_order_matrix(M, K):
+    """L = [[0, I], [-A, 0]] of section 3's first-order system, A = M^-1 K
+    by a LAPACK solve (not the oracle's Cholesky)."""
+    s = M.shape[0]
+    A = scipy.linalg.solve(M, K)
+    L = np.zeros((2 * s, 2 * s))
+    L[:s, s:] = np.eye(s)
+    L[s:, :s] = -A
+    return L
+
+
+@pytest.mark.parametrize("kind,s", [("chain", 1), ("chain", 2), ("chain", 5), ("dense", 3), ("dense", 6)])
+def test_rk4_propagator_is_degree4_taylor_polynomial(kind, s):
+    """Classic RK4 on y' = L y is exactly sum_{j<=4} (hL)^j / j! (the stage
+    form's algebra); the oracle's matrix, formed by stepping unit vectors,
+    matches it at h omega_max = 0.5, where higher terms would be visible."""
+    rng = np.random.default_rng(600 + s)
+    if kind == "chain":
+        a, b = _random_chain(rng, s)
+        M, K = cf.chain_matrices(a, b)
+    else:
+        M, K = workloads.random_dense_system(rng, s)
+        a, b = M, K
+    wmax = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    h = 0.5 / wmax
+    P = oracle.propagator("rk4", kind, a, b, h, 1)
+    hL = h * _first_order_matrix(M, K)
+    T = np.eye(2 * s)
+    term = np.eye(2 * s)
+    for j in range(1, 5):
+        term = term @ hL / j
+        T = T + term
+    scale = np.abs(T).max()
+    assert np.abs(P - T).max() <= 1e-13 * scale
+    # the fifth-order term is not there (it would be at this step size)
+    assert np.abs(P - (T + term @ hL / 5)).max() > 1e-4 * scale
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_propagator_eigenvalues_are_the_modal_amplification(method):
+    """On each normal mode (LAPACK eigh(K, M)) one step multiplies by
+    R(+-i theta) (RK4) or e^{+-i phi} with cos phi = 1 - theta^2/2 (Verlet),
+    theta = omega h."""
+    rng = np.random.default_rng(610)
+    s = 6
+    m, k = _random_chain(rng, s)
+    M, K = cf.chain_matrices(m, k)
+    w = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True))
+    h = 0.6 / w[-1]
+    P = oracle.propagator(method, "chain", m, k, h, 1)
+    th = w * h
+    if method == "rk4":
+        z = 1j * th
+        lam = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    else:
+        lam = np.exp(1j * np.arccos(1 - th ** 2 / 2))
+        assert np.linalg.det(P) == pytest.approx(1.0, abs=1e-12)   # area-preserving
+    ref = np.concatenate([lam, lam.conj()])
+    got = np.linalg.eigvals(P)
+    key = lambda v: (np.round(v.real, 9), np.round(v.imag, 9))
+    np.testing.assert_allclose(sorted(got, key=key), sorted(ref, key=key), atol=1e-12)
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_propagator_of_k_steps_is_the_kth_power_and_the_trajectory(method):
+    """P_k equals P_1 multiplied k times, and P_k y0 equals k steps of the
+    integrator from y0 (linearity of the scheme); k = 0 is the identity."""
+    rng = np.random.default_rng(620)
+    s = 4
+    M, K = workloads.random_dense_system(rng, s)
+    h = 0.2 / np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    P1 = oracle.propagator(method, "dense", M, K, h, 1)
+    Pk = oracle.propagator(method, "dense", M, K, h, 37)
+    np.testing.assert_allclose(Pk, np.linalg.matrix_power(P1, 37), atol=1e-12 * np.abs(Pk).max())
+    np.testing.assert_array_equal(oracle.propagator(method, "dense", M, K, h, 0), np.eye(2 * s))
+    x0, v0 = rng.normal(size=(1, s)), rng.normal(size=(1, s))
+    _, _, xe, ve = oracle.dense(method, M, K, [h], x0, v0, 37, 0)
+    y = Pk @ np.concatenate([x0[0], v0[0]])
+    np.testing.assert_allclose(np.concatenate([xe[0], ve[0]]), y, atol=1e-12 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("orig,mut", [
+    ("P[(size_t)i * n + j] = ye[i]", "P[(size_t)j * n + i] = ye[i]"),          # transposed
+    ("y0[i] = (i == j) ? 1.0 : 0.0", "y0[i] = (i == j) ? 1.0 : 0.5 * (i == j + 1)"),  # wrong start
+])
+def test_pins_catch_planted_propagator_mistakes(orig, mut, tmp_path):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "osc_oracle.c")).read()
+    assert orig in src
+    mpath = tmp_path / "mut.c"
+    mpath.write_text(src.replace(orig, mut))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(mpath), "-lm"], check=True)
+    import ctypes
+    L = ctypes.CDLL(str(lib))
+    d = ctypes.POINTER(ctypes.c_double)
+    L.oracle_propagator.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d, ctypes.c_double,
+                                    ctypes.c_int64, d]
+    rng = np.random.default_rng(630)
+    s = 3
+    M, K = workloads.random_dense_system(rng, s)
+    h = 0.5 / np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True)[-1])
+    P = np.empty((2 * s, 2 * s))
+    p = lambda a: a.ctypes.data_as(d)
+    Mc, Kc = np.ascontiguousarray(M), np.ascontiguousarray(K)
+    assert L.oracle_propagator(0, 1, s, p(Mc), p(Kc), h, 1, p(P)) == 0
+    hL = h * _first_order_matrix(M, K)
+    T = sum(np.linalg.matrix_power(hL, j) / math.factorial(j) for j in range(5))
+    assert np.abs(P - T).max() > 1e-6, "planted mistake not detected"
