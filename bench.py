@@ -5,7 +5,9 @@ Default workload (c3): 4096 fixed-free spring chains of s = 1024 bodies
 (eq. (2) generalised), masses U[0.5, 2], springs LogU[1e2, 1e4],
 x0 ~ N(0, sigma = 0.1), v0 = 0, dt = 0.01/omega_max per chain, 10^5 classic
 RK4 steps with FP32 state (synthetic, seeded): the largest configuration
-that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c4, c4v, c5).
+that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c4, c4v, c5;
+and the propagator modes: c2p, the per-step step matrix; c2j and c4j, frames
+by powers of the step matrix).
 
 One timed step is one pass of the whole hot path over the batch, with every
 input already resident in HBM: osc_create from device-resident FP64
@@ -59,7 +61,13 @@ DENSE_PRODUCTS = {"rk4": 4, "verlet": 1}
 DENSE_HW_TERMS = {"rk4": 7, "verlet": 3}     # MFMA products per step with the FP16 splits
 
 # oracle sample sizes (instance 0, the last instance and seeded others)
-CPU_SAMPLE = {"c1": 1, "c2": 65536, "c2v": 65536, "c3": 32, "c3v": 32, "c4": 256, "c4v": 256}
+CPU_SAMPLE = {"c1": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c4": 256,
+              "c4v": 256, "c4j": 256}
+# the per-step propagator's own count for two-mass RK4 at FP32: per DOF, dx
+# from the low parts, the w terms and the high parts of one row of the 4x4
+# step matrix (6 FMA) plus w (1 add), dw likewise (6 FMA), two compensated
+# sums (2 adds) and two state reads (2 adds)
+IMPL_PROP_STEP_FLOPS = 29
 
 WORKLOADS = {
     "c1": dict(kind="chain", method="rk4", prec="f64",
@@ -76,6 +84,15 @@ WORKLOADS = {
                desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, FP32 state, FP16x3 MFMA"),
     "c4v": dict(kind="dense", method="verlet", prec="f32",
                 desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 Verlet steps, FP32 state, FP16x3 MFMA"),
+    "c2p": dict(kind="chain", method="rk4", prec="f32", propagator=2,
+                desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 RK4 steps, FP32, "
+                     "per-step propagator (one 4x4 step matrix per instance)"),
+    "c2j": dict(kind="chain", method="rk4", prec="f32", propagator=1,
+                desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 RK4 steps, frames every 100 steps "
+                     "by powers of the step matrix (FP64 state, FP32 in/out)"),
+    "c4j": dict(kind="dense", method="rk4", prec="f32", propagator=1,
+                desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, frames every 1000 steps "
+                     "by powers of the step matrix (FP64 matrix cores, FP32 in/out)"),
     "c5": dict(kind="serve", method="rk4", prec="f32",
                desc="served stream: chains and dense SPD systems, s LogU[2,2048], nsteps LogU[1e3,1e5], FP32"),
 }
@@ -91,7 +108,7 @@ def make_workload(name):
         return workloads.c1_paper_two_mass(out_stride=1000)
     if name.startswith("c2"):
         w = workloads.c2_two_dof_ensemble()
-        w.out_stride = w.nsteps
+        w.out_stride = 100 if name == "c2j" else w.nsteps
         return w
     if name.startswith("c3"):
         w = workloads.c3_spring_chain()
@@ -165,6 +182,33 @@ def cpu_baseline(w, kind, method, prec, idx):
                 seconds=round(el, 3)), (xf, vf)
 
 
+def jump_roofline(w, kind, seconds):
+    """Frame jumps: the two-mass ensemble's one kernel moves its inputs, the
+    frames and the final state (HBM-bound); dense shared systems are FP64
+    matrix-core products: the powers of the step matrix by repeated squaring
+    (A^2, then squarings and multiplications of 2s x 2s matrices) and one
+    (batch x 2s) x (2s x 2s) product per frame."""
+    nf = w.nsteps // w.out_stride + 1 if w.out_stride else 0
+    rest = w.nsteps - (nf - 1) * w.out_stride if nf else w.nsteps
+    if kind == "chain":
+        elem = 4
+        per_inst = (w.s * 2 * 8 + 8) + 2 * w.s * elem + (nf + 1) * 2 * w.s * elem   # m, k, h; x0, v0; frames, end
+        byts = per_inst * w.batch
+        achieved = byts / seconds / 1e9
+        return dict(bound="hbm", achieved=round(achieved, 1), peak=8000.0, unit="GB/s",
+                    frac=round(achieved / 8000.0, 4), traffic=None, kernel="small_jump_kernel",
+                    kernel_ms=round(seconds * 1e3, 4), bytes_per_launch=int(byts))
+    n = 2 * w.s
+    squarings = max(int(w.out_stride if nf > 1 else 0).bit_length(), int(rest).bit_length()) - 1
+    gemms = max(squarings, 0) + max(bin(int(w.out_stride)).count("1") - 1, 0) * (nf > 1) \
+        + max(bin(int(rest)).count("1") - 1, 0) * (rest > 0)
+    flops = 2.0 * w.s ** 3 + gemms * 2.0 * n ** 3 + ((nf - 1) + (rest > 0)) * 2.0 * n * n * w.batch
+    achieved = flops / seconds / 1e12
+    return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK["fp64"], unit="TFLOP/s",
+                frac=round(achieved / PEAK["fp64"], 4), traffic=None, kernel="product_kernel (FP64)",
+                kernel_ms=round(seconds * 1e3, 4), flops_per_launch=flops, matrix_products=gemms)
+
+
 def bench_batched(args, name, spec):
     import numpy as np
     import torch
@@ -187,10 +231,16 @@ def bench_batched(args, name, spec):
     stream = torch.cuda.current_stream()
     kern_ms = []
 
+    mode = spec.get("propagator", 0)
+
     def make_system():
         if kind == "chain":
-            return osc.System("chain", method, prec, P1, P2, P3, stream=stream).create()
-        return osc.System("dense", method, prec, P1, P2, P3, shared=True, batch=w.batch, stream=stream).create()
+            sysm = osc.System("chain", method, prec, P1, P2, P3, stream=stream).create()
+        else:
+            sysm = osc.System("dense", method, prec, P1, P2, P3, shared=True, batch=w.batch, stream=stream).create()
+        if mode:
+            sysm.set_config(osc.CFG_PROPAGATOR, mode)
+        return sysm
 
     def one_step(record):
         sysm = make_system()
@@ -223,13 +273,16 @@ def bench_batched(args, name, spec):
     _log(f"[bench] {value:.4e} DOF-steps/s, {ms_per_step:.3f} ms/step")
 
     kavg = float(np.mean(kern_ms)) * 1e-3
-    if kind == "chain":
+    if mode == 1:
+        roofline = jump_roofline(w, kind, kavg)
+    elif kind == "chain":
         fpd = (ALG_CHAIN2_FLOPS if w.s == 2 else ALG_CHAIN_FLOPS)[method]
-        impl = IMPL_CHAIN_FLOPS[(method, prec)]
+        impl = IMPL_PROP_STEP_FLOPS if mode == 2 else IMPL_CHAIN_FLOPS[(method, prec)]
         achieved = fpd * dof_steps / kavg / 1e12
         peak = PEAK["fp32"] if prec == "f32" else PEAK["fp64"]
         roofline = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                        frac=round(achieved / peak, 4), traffic=measured_traffic(name), kernel="chain_kernel",
+                        frac=round(achieved / peak, 4), traffic=measured_traffic(name),
+                        kernel="prop_step_kernel" if mode == 2 else "chain_kernel",
                         kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd,
                         impl_flops_per_dof_step=impl,
                         impl_frac=round(impl * dof_steps / kavg / 1e12 / peak, 4))
@@ -249,7 +302,9 @@ def bench_batched(args, name, spec):
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": spec["desc"], "batch": w.batch, "s": w.s, "nsteps": w.nsteps,
-                   "method": method, "out_stride": w.out_stride},
+                   "method": method, "out_stride": w.out_stride,
+                   "mode": {0: "time stepping", 1: "frame jumps by powers of the step matrix",
+                            2: "per-step propagator"}[mode]},
         "roofline": roofline,
     }
 

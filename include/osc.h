@@ -184,6 +184,22 @@ osc_status osc_energy(osc_sys *sys, const void *x, const void *v, double *E);
 osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double *Q);
 
 /*
+ * osc_propagator -- the matrix of k steps of the handle's scheme.  For
+ * eq. (1) the first-order system of section 3 is y' = L y with the constant
+ * L = [[0, I], [-A, 0]], y = (x, v), so k steps of either scheme are one
+ * matrix: y_{n+k} = P_k y_n.  One RK4 step is the degree-4 Taylor polynomial
+ * of exp(hL): with B = h^2 A, C = I - B/2 + B^2/24, S = I - B/6,
+ *   P_1 = [[C, h S], [-(B - B^2/6)/h, C]];
+ * one velocity Verlet step is P_1 = [[I - B/2, h I], [-(B - B^2/4)/h, I - B/2]].
+ * P_k = P_1^k by repeated squaring, all in FP64 on the GPU.
+ * P: device double [nsys][2s][2s] row-major, positions first (nsys = batch
+ * for chains and per-instance dense systems, 1 for a shared operator).
+ * s <= 256 (OSC_ENOTSUP otherwise).  k = 0 gives the identity.  Ordered on
+ * the handle's stream; for s > 2 the call waits for its own temporaries.
+ */
+osc_status osc_propagator(osc_sys *sys, int64_t k, double *P);
+
+/*
  * osc_dense_operator -- copy A = M^-1 K of a dense handle, formed on the GPU
  * in FP64 by Cholesky (eq. (1)), to the device array A ([nsys][s][s]
  * row-major, nsys = 1 when shared, else batch).  Asynchronous.  OSC_EINVAL
@@ -208,6 +224,18 @@ osc_status osc_dense_operator(osc_sys *sys, double *A);
  *                             agree bitwise.
  *   OSC_CFG_GRAPH_STEPS       split dense path: steps per captured hipGraph
  *                             that is replayed (0 = launch eagerly; default 64).
+ *   OSC_CFG_PROPAGATOR        the scheme applied as its matrix (osc_propagator):
+ *                             0 off (default); 1 frame jumps: osc_integrate
+ *                             forms P^out_stride and advances from frame to
+ *                             frame by one product with it, the rest of the run
+ *                             by P^r (r = nsteps - last frame step; P^nsteps
+ *                             when out_stride == 0), with the state in FP64
+ *                             (s <= 256): the scheme's own trajectory at the
+ *                             frames, rounded differently and not computed at
+ *                             the steps in between; 2 per-step propagator for
+ *                             chains of s <= 2: each step applies P - I (FP32:
+ *                             split into high and low parts) to the compensated
+ *                             state.
  * Returns OSC_EINVAL for an unknown key or value, OSC_ENOTSUP for a layout or
  * kernel this handle cannot use.
  */
@@ -215,7 +243,8 @@ typedef enum {
     OSC_CFG_CHAIN_LAYOUT = 1,
     OSC_CFG_DENSE_KERNEL = 2,
     OSC_CFG_STEPS_PER_LAUNCH = 3,
-    OSC_CFG_GRAPH_STEPS = 4
+    OSC_CFG_GRAPH_STEPS = 4,
+    OSC_CFG_PROPAGATOR = 5
 } osc_config;
 osc_status osc_set_config(osc_sys *sys, osc_config key, int64_t value);
 

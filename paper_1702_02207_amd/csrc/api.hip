@@ -527,6 +527,56 @@ osc_status integrate_dense(osc_sys *s, const void *x0, const void *v0, int64_t n
                       [&](const DenseLaunch<T> &c) { return dense_launch_vec<T>(c, s->method, s->stream); });
 }
 
+PropArgs prop_args(const osc_sys *s) {
+    PropArgs a{};
+    a.kind = s->kind;
+    a.method = s->method;
+    a.nsys = s->kind == OSC_CHAIN ? s->batch : s->nsys;
+    a.m = s->kind == OSC_CHAIN ? s->m : nullptr;
+    a.k = s->kind == OSC_CHAIN ? s->k : nullptr;
+    a.A = s->kind == OSC_DENSE ? s->A : nullptr;
+    a.h = s->h;
+    return a;
+}
+
+// Frames by powers of the one-step matrix (OSC_CFG_PROPAGATOR = 1).
+template <typename T>
+osc_status integrate_jump(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride, void *xf,
+                          void *vf, void *xe, void *ve) {
+    PropRun<T> run{};
+    run.batch = s->batch;
+    run.nsteps = nsteps;
+    run.out_stride = out_stride;
+    run.x0 = static_cast<const T *>(x0);
+    run.v0 = static_cast<const T *>(v0);
+    run.xf = static_cast<T *>(xf);
+    run.vf = static_cast<T *>(vf);
+    run.xe = static_cast<T *>(xe);
+    run.ve = static_cast<T *>(ve);
+    run.nonfinite = s->flag;
+    return propagator_jump<T>(prop_args(s), s->s, run, s->stream);
+}
+
+// One application of the one-step matrix per step (OSC_CFG_PROPAGATOR = 2).
+template <typename T>
+osc_status integrate_prop_step(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                               void *xf, void *vf, void *xe, void *ve) {
+    ChainLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.c = coef_of<T>(s);
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.out_stride = out_stride;
+    a.xf = static_cast<T *>(xf);
+    a.vf = static_cast<T *>(vf);
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.nonfinite = s->flag;
+    return run_chunks(s, a, nsteps,
+                      [&](const ChainLaunch<T> &c) { return prop_step_launch<T>(c, s->method, s->stream); });
+}
+
 }  // namespace
 
 template <typename T>
@@ -667,6 +717,13 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
             if (value < 0 || value > 4096) return fail(OSC_EINVAL, "graph steps must be in [0, 4096]");
             s->graph_steps = value;
             return OSC_OK;
+        case OSC_CFG_PROPAGATOR:
+            if (value < 0 || value > 2) return fail(OSC_EINVAL, "propagator mode must be 0, 1 or 2");
+            if (value == 1 && s->s > 256) return fail(OSC_ENOTSUP, "frame jumps take s <= 256");
+            if (value == 2 && !(s->kind == OSC_CHAIN && s->s <= 2))
+                return fail(OSC_ENOTSUP, "the per-step propagator takes chains of s <= 2");
+            s->propagator = (int)value;
+            return OSC_OK;
     }
     return fail(OSC_EINVAL, "unknown configuration key");
 }
@@ -683,6 +740,12 @@ static osc_status integrate_checks(osc_sys *s, const void *x0, const void *v0, i
 
 static osc_status integrate_any(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
                                 void *xf, void *vf, void *xe, void *ve) {
+    if (s->propagator == 1)
+        return s->prec == OSC_F32 ? integrate_jump<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
+                                  : integrate_jump<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
+    if (s->propagator == 2)
+        return s->prec == OSC_F32 ? integrate_prop_step<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
+                                  : integrate_prop_step<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
     if (s->kind == OSC_DENSE)
         return s->prec == OSC_F32 ? integrate_dense<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                                   : integrate_dense<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
@@ -705,10 +768,15 @@ osc_status osc_integrate_static(osc_sys *s, const void *x0, const void *v0, int6
     if (r || s->batch == 0) return r;
     // device memory the run needs beyond its inputs and outputs
     size_t need_state = 0, need_split = 0;
-    if (s->kind == OSC_DENSE && use_mfma(s) && !s->shared)
+    if (s->propagator == 1 && !propagator_small(s->s))
+        return fail(OSC_ENOTSUP, "osc_integrate_static: frame jumps of systems with s > 2 form their matrix powers "
+                                 "in per-call buffers; use osc_integrate");
+    if (s->propagator == 0 && s->kind == OSC_DENSE && use_mfma(s) && !s->shared)
         return fail(OSC_ENOTSUP, "osc_integrate_static: per-instance operators on the matrix cores take a work "
                                  "list built per call; use osc_integrate");
-    if (s->kind == OSC_DENSE && !use_mfma(s) && use_split(s)) {
+    if (s->propagator == 1) {
+        // one kernel per call, no scratch
+    } else if (s->propagator == 0 && s->kind == OSC_DENSE && !use_mfma(s) && use_split(s)) {
         need_state = state_bytes(s);
         need_split = dense_split_scratch_elems(s->s, s->batch) * elem(s) + 64;
     } else if (s->steps_per_launch > 0 && nsteps > s->steps_per_launch) {
@@ -770,6 +838,15 @@ osc_status osc_energy(osc_sys *s, const void *x, const void *v, double *E) { ret
 
 osc_status osc_shadow_energy(osc_sys *s, const void *x, const void *v, double *Q) {
     return energy_common(s, x, v, Q, true);
+}
+
+osc_status osc_propagator(osc_sys *s, int64_t k, double *P) {
+    g_last_error.clear();
+    if (!s || !P) return fail(OSC_EINVAL, "handle and P must be non-NULL");
+    if (k < 0) return fail(OSC_EINVAL, "k must be >= 0");
+    if (s->s > 256) return fail(OSC_ENOTSUP, "osc_propagator takes s <= 256");
+    if (s->batch == 0) return OSC_OK;
+    return propagator_matrix(prop_args(s), s->s, k, P, s->stream);
 }
 
 osc_status osc_dense_operator(osc_sys *s, double *A) {

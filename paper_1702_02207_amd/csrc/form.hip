@@ -231,8 +231,9 @@ __global__ void __launch_bounds__(256) panel_kernel(Panel P) {
 // at B[p*b_p + j*b_j], (i, j) of C at C[i*c_i + j*c_j]; system z adds z times
 // the *_sys strides.  One 256-thread workgroup per 64x64 tile of C (lower
 // tiles only when `lower`), each wave a 32x32 quarter as 2x2 MFMA 16x16x4
-// blocks.  A tile reads all of its operands before it writes, so C may alias
-// A (when n <= 64) or B (when m <= 64).
+// blocks; the k dimension runs in chunks of 64 staged through LDS.  A tile
+// reads all of its operands before it writes, so C may alias A (when
+// n <= 64) or B (when m <= 64).
 struct Product {
     int m, n, k;
     int tiles_n;
@@ -283,20 +284,7 @@ __global__ void __launch_bounds__(256) product_kernel(ProductPair pp) {
     const double *B = g.B + sys * g.b_sys + j0 * g.b_j;
     double *C = g.C + sys * g.c_sys + i0 * g.c_i + j0 * g.c_j;
     const int m = min(kNb, g.m - i0), n = min(kNb, g.n - j0);
-    stage_tile(sa, A, g.a_i, g.a_p, m, g.k, tid);
-    // B staged as [p][j]: its "q" index is j
-    if (g.b_j == 1) {
-        for (int idx = tid; idx < kNb * kNb; idx += 256) {
-            const int j = idx % kNb, p = idx / kNb;
-            sb[p][j] = (j < n && p < g.k) ? B[j + p * g.b_p] : 0.0;
-        }
-    } else {
-        for (int idx = tid; idx < kNb * kNb; idx += 256) {
-            const int p = idx % kNb, j = idx / kNb;
-            sb[p][j] = (j < n && p < g.k) ? B[j * g.b_j + p * g.b_p] : 0.0;
-        }
-    }
-    // the old C values load while the operands stage
+    // the old C values load while the first operands stage
     double old[2][2][4];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
@@ -304,10 +292,28 @@ __global__ void __launch_bounds__(256) product_kernel(ProductPair pp) {
                 const int i = acc_row(wi, a, lane, r), j = acc_col(wj, b, lane);
                 old[a][b][r] = (!g.overwrite && i < m && j < n) ? C[i * g.c_i + j * g.c_j] : 0.0;
             }
-    __syncthreads();
     v4d acc[2][2];
     zero_acc(acc);
-    mfma_tile(sa, sb, g.k, wi, wj, lane, acc);
+    for (int p0 = 0; p0 < g.k; p0 += kNb) {
+        const int kc = min(kNb, g.k - p0);
+        if (p0 > 0) __syncthreads();   // every wave is done with the previous chunk
+        stage_tile(sa, A + p0 * g.a_p, g.a_i, g.a_p, m, kc, tid);
+        // B staged as [p][j]: its "q" index is j
+        const double *Bp = B + p0 * g.b_p;
+        if (g.b_j == 1) {
+            for (int idx = tid; idx < kNb * kNb; idx += 256) {
+                const int j = idx % kNb, p = idx / kNb;
+                sb[p][j] = (j < n && p < kc) ? Bp[j + p * g.b_p] : 0.0;
+            }
+        } else {
+            for (int idx = tid; idx < kNb * kNb; idx += 256) {
+                const int p = idx % kNb, j = idx / kNb;
+                sb[p][j] = (j < n && p < kc) ? Bp[j * g.b_j + p * g.b_p] : 0.0;
+            }
+        }
+        __syncthreads();
+        mfma_tile(sa, sb, kc, wi, wj, lane, acc);
+    }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int r = 0; r < 4; ++r) acc[a][b][r] = g.overwrite ? acc[a][b][r] : old[a][b][r] - acc[a][b][r];
@@ -342,6 +348,16 @@ osc_status run_products(Product g0, Product g1, int64_t nsys, hipStream_t st) {
 }
 
 }  // namespace
+
+osc_status gemm64(const Gemm64 &p, int64_t nsys, hipStream_t st) {
+    Product g{};
+    g.m = p.m, g.n = p.n, g.k = p.k;
+    g.overwrite = p.overwrite;
+    g.A = p.A, g.a_i = p.a_i, g.a_p = p.a_p, g.a_sys = p.a_sys;
+    g.B = p.B, g.b_p = p.b_p, g.b_j = p.b_j, g.b_sys = p.b_sys;
+    g.C = p.C, g.c_i = p.c_i, g.c_j = p.c_j, g.c_sys = p.c_sys;
+    return run_products(g, Product{}, nsys, st);
+}
 
 size_t dense_form_scratch_elems(int s) {
     return (size_t)((s + kNb - 1) / kNb) * kNb * kNb;

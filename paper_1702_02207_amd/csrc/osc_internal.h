@@ -183,6 +183,24 @@ int dense_vec_bucket(int s);
 size_t dense_form_scratch_elems(int s);
 osc_status dense_form_a(int s, int64_t nsys, const double *M, const double *K, double *Lc, double *Inv, double *A,
                         int *status, hipStream_t st);
+// Batched FP64 product on the matrix cores: C = A B (overwrite) or C -= A B,
+// element (i, p) of A at A[i*a_i + p*a_p], (p, j) of B at B[p*b_p + j*b_j],
+// (i, j) of C at C[i*c_i + j*c_j]; system z adds z times the *_sys strides.
+// C may alias A only when n <= 64, B only when m <= 64.
+struct Gemm64 {
+    int m, n, k;
+    int overwrite;
+    const double *A;
+    int64_t a_i, a_p;
+    size_t a_sys;
+    const double *B;
+    int64_t b_p, b_j;
+    size_t b_sys;
+    double *C;
+    int64_t c_i, c_j;
+    size_t c_sys;
+};
+osc_status gemm64(const Gemm64 &g, int64_t nsys, hipStream_t st);
 // B = h^2 A (column-major, split for FP32) and per-system row-sum bounds
 // theta[sys] >= h omega_max.
 template <typename T>
@@ -249,6 +267,34 @@ size_t dense_mfma_fragment_elems(int s);         // FP16 elements per operator p
 osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *B1, _Float16 *B2, hipStream_t st);
 osc_status dense_mfma_launch(const DenseMfmaLaunch &a, int method, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// the schemes as matrices (propagator.hip)
+// ---------------------------------------------------------------------------
+struct PropArgs {
+    int kind, method;
+    int64_t nsys;              // systems: chains and per-instance dense = batch, shared dense = 1
+    const double *m, *k;       // chains: [nsys][s] masses and springs
+    const double *A;           // dense: [nsys][s][s] A = M^-1 K
+    const double *h;           // [nsys]
+};
+template <typename T>
+struct PropRun {
+    int64_t batch, nsteps, out_stride;
+    const T *x0, *v0;
+    T *xf, *vf, *xe, *ve;
+    int *nonfinite;
+};
+bool propagator_small(int s);   // s <= 2: one lane per system, P in registers
+// P^k of every system, [nsys][2s][2s] row-major on (x, v), FP64.
+osc_status propagator_matrix(const PropArgs &a, int s, int64_t k, double *out, hipStream_t st);
+// Frames by P^out_stride, the rest of the run by P^r (FP64 state).
+template <typename T>
+osc_status propagator_jump(const PropArgs &a, int s, const PropRun<T> &run, hipStream_t st);
+// Per-step propagator for chains of s <= 2 (same launch arguments and state
+// planes as the chain kernel).
+template <typename T>
+osc_status prop_step_launch(const ChainLaunch<T> &a, int method, hipStream_t st);
+
 // runtime helpers shared by the server (api.hip)
 template <typename T>
 ChainCoef<T> chain_coef(const osc_sys *s);
@@ -304,6 +350,7 @@ struct osc_sys {
     // and the split path's buffers are parts of the library's static device
     // scratch instead of the handle's own (allocated on demand), and no graph
     // is captured
+    int propagator = 0;                  // OSC_CFG_PROPAGATOR: 0 off, 1 frame jumps, 2 per-step (chains s <= 2)
     bool static_call = false;
     void *scratch_state = nullptr;
     void *scratch_split = nullptr;

@@ -25,7 +25,7 @@ KINDS = {"chain": 0, "dense": 1}
 METHODS = {"rk4": 0, "verlet": 1}
 PRECS = {"f64": 0, "f32": 1}
 MEM_HOST, MEM_DEVICE = 0, 1
-CFG_CHAIN_LAYOUT, CFG_DENSE_KERNEL, CFG_STEPS_PER_LAUNCH, CFG_GRAPH_STEPS = 1, 2, 3, 4
+CFG_CHAIN_LAYOUT, CFG_DENSE_KERNEL, CFG_STEPS_PER_LAUNCH, CFG_GRAPH_STEPS, CFG_PROPAGATOR = 1, 2, 3, 4, 5
 
 
 class OscError(RuntimeError):
@@ -79,6 +79,7 @@ def load():
         "osc_shadow_energy": (i32, [vp, vp, vp, vp]),
         "osc_sync": (i32, [vp]),
         "osc_dense_operator": (i32, [vp, vp]),
+        "osc_propagator": (i32, [vp, i64, vp]),
         "osc_set_config": (i32, [vp, i32, i64]),
         "osc_autotune": (i32, [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]),
         "osc_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
@@ -273,6 +274,19 @@ class System:
         chosen = ctypes.c_int64(0)
         _check(load().osc_autotune(self.handle, _dptr(x0), _dptr(v0), int(probe_steps), ctypes.byref(chosen)))
         return chosen.value
+
+    def propagator(self, k: int = 1):
+        """osc_propagator: the FP64 matrix of k steps on (x, v), a new device
+        tensor [nsys, 2s, 2s] (nsys = batch, or 1 for a shared operator)."""
+        import torch
+        if self.handle is None:
+            raise ValueError("the system has not been created (call create())")
+        if k < 0:
+            raise ValueError("k must be >= 0")
+        nsys = 1 if (self.kind == "dense" and self._shared) else self.batch
+        P = torch.empty((nsys, 2 * self.s, 2 * self.s), dtype=torch.float64, device="cuda")
+        _check(load().osc_propagator(self.handle, int(k), _dptr(P)))
+        return P
 
     def dense_operator(self):
         """A = M^-1 K as formed on the GPU (FP64), [nsys, s, s]."""
