@@ -53,7 +53,12 @@ def _load():
     lib.oracle_verlet_q_chain.argtypes = [i64, i32, d, d, d, d, d, d]
     lib.oracle_verlet_q_dense.argtypes = [i64, i32, i32, d, d, d, d, d, d]
     lib.oracle_propagator.argtypes = [i32, i32, i32, d, d, ctypes.c_double, i64, d]
-    for f in ("oracle_propagator", "oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
+    dbl = ctypes.c_double
+    lib.oracle_chain_driven.argtypes = [i64, i32, d, d, d, dbl, dbl, d, d, d, d, i64, i64, d, d, d, d]
+    lib.oracle_dense_driven.argtypes = [i64, i32, i32, d, d, d, dbl, dbl, d, d, d, d, i64, i64, d, d, d, d]
+    lib.oracle_dopri_driven.argtypes = [i32, i32, d, d, dbl, dbl, d, dbl, d, d, dbl, i32, dbl, dbl, d, d,
+                                        ctypes.POINTER(ctypes.c_int64)]
+    for f in ("oracle_chain_driven", "oracle_dense_driven", "oracle_dopri_driven", "oracle_propagator", "oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
               "oracle_energy_dense", "oracle_verlet_q_chain", "oracle_verlet_q_dense"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -179,6 +184,68 @@ def propagator(method, kind, a, b, dt, k=1):
     _check(lib.oracle_propagator(_METHODS[method], {"chain": 0, "dense": 1}[kind], s, _p(a), _p(b),
                                  float(dt), int(k), _p(P)), "oracle_propagator")
     return P
+
+
+def _driven_force(F, omega, batch):
+    if F is None:
+        return None, None
+    F = _f64(F).reshape(batch, -1)
+    omega = _f64(np.broadcast_to(np.atleast_1d(omega), (batch,)))
+    return F, omega
+
+
+def chain_driven(m, k, dt, alpha, beta, F, omega, x0, v0, nsteps, stride, frames=True):
+    """Classic RK4 for damped, driven chains: M x'' + (alpha M + beta K) x' +
+    K x = F cos(omega t).  F [batch, s] forces (None: no force), omega [batch]
+    (or a scalar).  Returns (x_frames, v_frames, x_end, v_end)."""
+    lib = _load()
+    m, k, dt, x0, v0 = map(_f64, (m, k, dt, x0, v0))
+    batch, s = x0.shape
+    F, omega = _driven_force(F, omega, batch)
+    nf = _nframes(nsteps, stride) if frames else 0
+    xf = np.empty((nf, batch, s)) if nf else None
+    vf = np.empty((nf, batch, s)) if nf else None
+    xe, ve = np.empty((batch, s)), np.empty((batch, s))
+    st = lib.oracle_chain_driven(batch, s, _p(m), _p(k), _p(dt), float(alpha), float(beta), _p(F), _p(omega),
+                                 _p(x0), _p(v0), int(nsteps), int(stride) if nf else 0,
+                                 _p(xf), _p(vf), _p(xe), _p(ve))
+    _check(st, "oracle_chain_driven")
+    return xf, vf, xe, ve
+
+
+def dense_driven(M, K, dt, alpha, beta, F, omega, x0, v0, nsteps, stride, shared=True, frames=True):
+    """Classic RK4 for damped, driven dense systems (f = M^-1 F by Cholesky)."""
+    lib = _load()
+    M, K, dt, x0, v0 = map(_f64, (M, K, np.atleast_1d(dt), x0, v0))
+    batch, s = x0.shape
+    F, omega = _driven_force(F, omega, batch)
+    nf = _nframes(nsteps, stride) if frames else 0
+    xf = np.empty((nf, batch, s)) if nf else None
+    vf = np.empty((nf, batch, s)) if nf else None
+    xe, ve = np.empty((batch, s)), np.empty((batch, s))
+    st = lib.oracle_dense_driven(batch, s, 1 if shared else 0, _p(M), _p(K), _p(dt), float(alpha), float(beta),
+                                 _p(F), _p(omega), _p(x0), _p(v0), int(nsteps), int(stride) if nf else 0,
+                                 _p(xf), _p(vf), _p(xe), _p(ve))
+    _check(st, "oracle_dense_driven")
+    return xf, vf, xe, ve
+
+
+def dopri_driven(kind, a, b, alpha, beta, F, omega, x0, v0, t_end, nout, rtol=1e-10, atol=1e-12):
+    """Adaptive Dormand-Prince 5(4) reference for one damped, driven instance
+    (kind "chain": a = m, b = k; "dense": a = M, b = K).  Returns
+    (x [nout+1, s], v [nout+1, s], accepted steps, rejected steps) at
+    t_j = j t_end / nout."""
+    lib = _load()
+    a, b, x0, v0 = map(_f64, (a, b, x0, v0))
+    s = x0.shape[-1]
+    Fp = None if F is None else _f64(F).reshape(s)
+    xo, vo = np.empty((nout + 1, s)), np.empty((nout + 1, s))
+    stats = (ctypes.c_int64 * 2)()
+    st = lib.oracle_dopri_driven({"chain": 0, "dense": 1}[kind], s, _p(a), _p(b), float(alpha), float(beta),
+                                 _p(Fp), float(omega), _p(x0.reshape(s)), _p(v0.reshape(s)), float(t_end),
+                                 int(nout), float(rtol), float(atol), _p(xo), _p(vo), stats)
+    _check(st, "oracle_dopri_driven")
+    return xo, vo, int(stats[0]), int(stats[1])
 
 
 def rel_traj_err(got, ref):

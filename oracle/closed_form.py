@@ -153,3 +153,68 @@ def rk4_energy_factor(theta):
     """|R(-i theta)|^2 = 1 - theta^6/72 + theta^8/576: the per-step energy factor of RK4."""
     theta = np.asarray(theta, dtype=np.float64)
     return 1.0 - theta ** 6 / 72.0 + theta ** 8 / 576.0
+
+
+# --------------------------------------------------------------------------
+# damped, driven systems: M x'' + (alpha M + beta K) x' + K x = F cos(W t)
+# --------------------------------------------------------------------------
+
+def _modes(M, K):
+    """omega^2 and M-orthonormal mode shapes of the pencil (K, M) (LAPACK)."""
+    w2, Phi = scipy.linalg.eigh(K, M)
+    return w2, Phi
+
+
+def driven_modal_solution(t, M, K, alpha, beta, F, W, x0, v0):
+    """Exact solution by normal modes.  Mode k obeys q'' + g_k q' + w_k^2 q =
+    f_k cos(W t) with g_k = alpha + beta w_k^2, f = Phi^T F.  Particular part
+    Re(G e^{iWt}), G = f / (w^2 - W^2 + i g W) (the receptance); the
+    homogeneous part from its initial value by the 2x2 matrix exponential of
+    [[0, 1], [-w^2, -g]] (scipy.linalg.expm).  Returns (x, v), [len(t), s]."""
+    t = np.asarray(t, dtype=np.float64)
+    w2, Phi = _modes(M, K)
+    q0 = Phi.T @ (M @ np.asarray(x0, dtype=np.float64))
+    p0 = Phi.T @ (M @ np.asarray(v0, dtype=np.float64))
+    fk = Phi.T @ (np.zeros(len(w2)) if F is None else np.asarray(F, dtype=np.float64))
+    g = alpha + beta * w2
+    G = fk / (w2 - W * W + 1j * g * W)
+    q = np.empty((len(t), len(w2)))
+    p = np.empty_like(q)
+    for k in range(len(w2)):
+        L = np.array([[0.0, 1.0], [-w2[k], -g[k]]])
+        z0 = np.array([q0[k] - G[k].real, p0[k] + W * G[k].imag])
+        for i, ti in enumerate(t):
+            z = scipy.linalg.expm(L * ti) @ z0
+            e = G[k] * np.exp(1j * W * ti)
+            q[i, k] = z[0] + e.real
+            p[i, k] = z[1] + (1j * W * e).real
+    return q @ Phi.T, p @ Phi.T
+
+
+def steady_amplitude(M, K, alpha, beta, F, W):
+    """|G_k| = |f_k| / sqrt((w_k^2 - W^2)^2 + (g_k W)^2) per mode: the
+    amplitude of the driven response once the transient has decayed."""
+    w2, Phi = _modes(M, K)
+    fk = Phi.T @ np.asarray(F, dtype=np.float64)
+    g = alpha + beta * w2
+    return np.abs(fk) / np.sqrt((w2 - W * W) ** 2 + (g * W) ** 2)
+
+
+def rk4_damped_discrete(steps, h, M, K, alpha, beta, x0, v0):
+    """Exact discrete solution of classic RK4 on the free damped system: per
+    mode the step multiplies (q, q') by R(hL_k) = sum_{j<=4} (hL_k)^j / j!,
+    L_k = [[0, 1], [-w_k^2, -g_k]]."""
+    w2, Phi = _modes(M, K)
+    q0 = Phi.T @ (M @ np.asarray(x0, dtype=np.float64))
+    p0 = Phi.T @ (M @ np.asarray(v0, dtype=np.float64))
+    g = alpha + beta * w2
+    steps = np.asarray(steps)
+    q = np.empty((len(steps), len(w2)))
+    p = np.empty_like(q)
+    for k in range(len(w2)):
+        hL = h * np.array([[0.0, 1.0], [-w2[k], -g[k]]])
+        R = np.eye(2) + hL + hL @ hL / 2 + hL @ hL @ hL / 6 + hL @ hL @ hL @ hL / 24
+        for i, n in enumerate(steps):
+            z = np.linalg.matrix_power(R, int(n)) @ np.array([q0[k], p0[k]])
+            q[i, k], p[i, k] = z
+    return q @ Phi.T, p @ Phi.T

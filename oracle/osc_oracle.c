@@ -446,3 +446,300 @@ int oracle_propagator(int method, int kind, int s, const double *a, const double
     free(A);
     return fail;
 }
+
+/* ----------------------------------------------------------------------- */
+/* damped and driven systems                                                 */
+/* ----------------------------------------------------------------------- */
+
+/* Beyond the paper's free vibrations (eq. (1)): Rayleigh damping C = alpha M
+ * + beta K and a harmonic force F cos(Omega t),
+ *     M x'' + C x' + K x = F cos(Omega t),
+ * i.e. in the first-order form of section 3
+ *     x' = v,   v' = -A x - (alpha v + beta A v) + f cos(Omega t),  f = M^-1 F.
+ * With alpha = beta = 0 and no force the acceleration is computed by the same
+ * operations as above, so the results equal those of the free integrator. */
+typedef struct {
+    double alpha, beta, omega;
+    const double *f;     /* [s] or NULL */
+} drive_t;
+
+static void accel_driven(const rhs_t *r, const drive_t *d, double t, const double *x, const double *v,
+                         double *a, double *tmp) {
+    accel(r, x, a);                                  /* -A x */
+    if (d->alpha != 0.0 || d->beta != 0.0) {
+        accel(r, v, tmp);                            /* -A v */
+        for (int i = 0; i < r->s; ++i) a[i] += -d->alpha * v[i] + d->beta * tmp[i];
+    }
+    if (d->f) {
+        const double c = cos(d->omega * t);
+        for (int i = 0; i < r->s; ++i) a[i] += d->f[i] * c;
+    }
+}
+
+/* Classic RK4 on the driven first-order system; the stages are evaluated at
+ * t_n, t_n + h/2, t_n + h/2 and t_n + h with t_n = n h. */
+#define ORC_DRIVEN_WORK_PER_DOF 13
+static void integrate_driven_one(const rhs_t *r, const drive_t *d, double h, const double *x0,
+                                 const double *v0, int64_t nsteps, int64_t stride, int64_t batch,
+                                 int64_t b, double *xf, double *vf, double *xe, double *ve, double *work) {
+    const int s = r->s;
+    double *x = work, *v = work + s;
+    double *k1x = work + 2 * s, *k1v = work + 3 * s, *k2x = work + 4 * s, *k2v = work + 5 * s;
+    double *k3x = work + 6 * s, *k3v = work + 7 * s, *k4x = work + 8 * s, *k4v = work + 9 * s;
+    double *xt = work + 10 * s, *vt = work + 11 * s, *tmp = work + 12 * s;
+    memcpy(x, x0, sizeof(double) * s);
+    memcpy(v, v0, sizeof(double) * s);
+    int64_t frame = 0;
+    if (stride > 0) {
+        store_frame(xf, batch, b, s, frame, x);
+        store_frame(vf, batch, b, s, frame, v);
+        ++frame;
+    }
+    for (int64_t n = 0; n < nsteps; ++n) {
+        const double t = (double)n * h;
+        for (int i = 0; i < s; ++i) k1x[i] = v[i];
+        accel_driven(r, d, t, x, v, k1v, tmp);
+        for (int i = 0; i < s; ++i) { xt[i] = x[i] + 0.5 * h * k1x[i]; vt[i] = v[i] + 0.5 * h * k1v[i]; }
+        for (int i = 0; i < s; ++i) k2x[i] = vt[i];
+        accel_driven(r, d, t + 0.5 * h, xt, vt, k2v, tmp);
+        for (int i = 0; i < s; ++i) { xt[i] = x[i] + 0.5 * h * k2x[i]; vt[i] = v[i] + 0.5 * h * k2v[i]; }
+        for (int i = 0; i < s; ++i) k3x[i] = vt[i];
+        accel_driven(r, d, t + 0.5 * h, xt, vt, k3v, tmp);
+        for (int i = 0; i < s; ++i) { xt[i] = x[i] + h * k3x[i]; vt[i] = v[i] + h * k3v[i]; }
+        for (int i = 0; i < s; ++i) k4x[i] = vt[i];
+        accel_driven(r, d, t + h, xt, vt, k4v, tmp);
+        for (int i = 0; i < s; ++i) {
+            x[i] += h / 6.0 * (k1x[i] + 2.0 * k2x[i] + 2.0 * k3x[i] + k4x[i]);
+            v[i] += h / 6.0 * (k1v[i] + 2.0 * k2v[i] + 2.0 * k3v[i] + k4v[i]);
+        }
+        if (stride > 0 && (n + 1) % stride == 0) {
+            store_frame(xf, batch, b, s, frame, x);
+            store_frame(vf, batch, b, s, frame, v);
+            ++frame;
+        }
+    }
+    if (xe) memcpy(xe + (size_t)b * s, x, sizeof(double) * s);
+    if (ve) memcpy(ve + (size_t)b * s, v, sizeof(double) * s);
+}
+
+/* f = M^-1 F for a dense SPD M (Cholesky, forward and back substitution). */
+static int solve_spd(int s, const double *M, const double *F, double *f, double *L, double *y) {
+    int st = cholesky(s, M, L);
+    if (st) return st;
+    for (int i = 0; i < s; ++i) {
+        double e = F[i];
+        for (int p = 0; p < i; ++p) e -= L[(size_t)i * s + p] * y[p];
+        y[i] = e / L[(size_t)i * s + i];
+    }
+    for (int i = s - 1; i >= 0; --i) {
+        double e = y[i];
+        for (int p = i + 1; p < s; ++p) e -= L[(size_t)p * s + i] * f[p];
+        f[i] = e / L[(size_t)i * s + i];
+    }
+    return ORC_OK;
+}
+
+/* Driven chains: m, k, F [batch][s] (F may be NULL), dt, omega [batch]. */
+int oracle_chain_driven(int64_t batch, int s, const double *m, const double *k, const double *dt,
+                        double alpha, double beta, const double *F, const double *omega,
+                        const double *x0, const double *v0, int64_t nsteps, int64_t stride,
+                        double *xf, double *vf, double *xe, double *ve) {
+    int st = check_common(ORC_RK4, batch, s, dt, x0, v0, nsteps, stride);
+    if (st) return st;
+    if (batch > 0 && (!m || !k || (F && !omega))) return ORC_EINVAL;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * ORC_DRIVEN_WORK_PER_DOF * (size_t)s);
+        double *f = (double *)malloc(sizeof(double) * s);
+        if (!work || !f) {
+#pragma omp atomic write
+            fail = ORC_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t b = 0; b < batch; ++b) {
+                const double *mb = m + (size_t)b * s;
+                if (F)
+                    for (int i = 0; i < s; ++i) f[i] = F[(size_t)b * s + i] / mb[i];
+                drive_t d = {alpha, beta, F ? omega[b] : 0.0, F ? f : NULL};
+                rhs_t r = {0, s, mb, k + (size_t)b * s, NULL};
+                integrate_driven_one(&r, &d, dt[b], x0 + (size_t)b * s, v0 + (size_t)b * s, nsteps, stride,
+                                     batch, b, xf, vf, xe, ve, work);
+            }
+        }
+        free(work);
+        free(f);
+    }
+    return fail;
+}
+
+/* Driven dense systems: M, K shared [s][s] (dt[0]) or per instance; F [batch][s]
+ * (may be NULL), omega [batch]. */
+int oracle_dense_driven(int64_t batch, int s, int shared, const double *M, const double *K,
+                        const double *dt, double alpha, double beta, const double *F,
+                        const double *omega, const double *x0, const double *v0, int64_t nsteps,
+                        int64_t stride, double *xf, double *vf, double *xe, double *ve) {
+    int st = check_common(ORC_RK4, batch, s, dt, x0, v0, nsteps, stride);
+    if (st) return st;
+    if (batch > 0 && (!M || !K || (F && !omega))) return ORC_EINVAL;
+    const size_t ss = (size_t)s * s;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * ORC_DRIVEN_WORK_PER_DOF * (size_t)s);
+        double *A = (double *)malloc(sizeof(double) * ss);
+        double *L = (double *)malloc(sizeof(double) * ss);
+        double *f = (double *)malloc(sizeof(double) * s);
+        double *y = (double *)malloc(sizeof(double) * s);
+        if (!work || !A || !L || !f || !y) {
+#pragma omp atomic write
+            fail = ORC_ENOMEM;
+        } else {
+            int64_t formed = -1;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t b = 0; b < batch; ++b) {
+                const int64_t sys = shared ? 0 : b;
+                const double *Mb = M + sys * ss, *Kb = K + sys * ss;
+                int e = ORC_OK;
+                if (formed != sys) {
+                    e = oracle_form_a(s, Mb, Kb, A);
+                    formed = sys;
+                }
+                if (!e && F) e = solve_spd(s, Mb, F + (size_t)b * s, f, L, y);
+                if (e) {
+#pragma omp atomic write
+                    fail = e;
+                    formed = -1;
+                    continue;
+                }
+                drive_t d = {alpha, beta, F ? omega[b] : 0.0, F ? f : NULL};
+                rhs_t r = {1, s, NULL, NULL, A};
+                integrate_driven_one(&r, &d, shared ? dt[0] : dt[b], x0 + (size_t)b * s, v0 + (size_t)b * s,
+                                     nsteps, stride, batch, b, xf, vf, xe, ve, work);
+            }
+        }
+        free(work);
+        free(A);
+        free(L);
+        free(f);
+        free(y);
+    }
+    return fail;
+}
+
+/* ----------------------------------------------------------------------- */
+/* adaptive reference: Dormand-Prince 5(4)                                   */
+/* ----------------------------------------------------------------------- */
+
+/* The explicit embedded Runge-Kutta pair of Dormand and Prince (1980), the
+ * method behind MATLAB's ode45, with which section 3 integrates its model:
+ * seven stages (the last one reused as the first of the next step), the
+ * fifth-order solution propagated, the difference to the fourth-order one as
+ * the error estimate.  Error norm: root mean square over the 2s components of
+ * err_i / (atol + rtol max(|y_i|, |y_new_i|)); a step is accepted when the
+ * norm is <= 1, and the next step is h * min(5, max(0.2, 0.9 norm^-1/5)).
+ * Output at t_j = j t_end / nout (j = 0..nout): steps are shortened to land on
+ * each output time.  One instance of a chain (kind 0: a = m, b = k) or a dense
+ * system (kind 1: a = M, b = K), damped and driven as above (F may be NULL).
+ * xo, vo: [nout+1][s].  stats: accepted and rejected steps. */
+int oracle_dopri_driven(int kind, int s, const double *a, const double *b, double alpha, double beta,
+                        const double *F, double omega, const double *x0, const double *v0, double t_end,
+                        int nout, double rtol, double atol, double *xo, double *vo, int64_t *stats) {
+    static const double c2 = 1.0 / 5, c3 = 3.0 / 10, c4 = 4.0 / 5, c5 = 8.0 / 9;
+    static const double a21 = 1.0 / 5;
+    static const double a31 = 3.0 / 40, a32 = 9.0 / 40;
+    static const double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+    static const double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
+    static const double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
+                        a65 = -5103.0 / 18656;
+    static const double a71 = 35.0 / 384, a73 = 500.0 / 1113, a74 = 125.0 / 192, a75 = -2187.0 / 6784,
+                        a76 = 11.0 / 84;
+    static const double e1 = 71.0 / 57600, e3 = -71.0 / 16695, e4 = 71.0 / 1920, e5 = -17253.0 / 339200,
+                        e6 = 22.0 / 525, e7 = -1.0 / 40;
+    if ((kind != 0 && kind != 1) || s < 1 || nout < 1 || !(t_end > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) ||
+        !a || !b || !x0 || !v0 || !xo || !vo)
+        return ORC_EINVAL;
+    const int n = 2 * s;
+    const size_t ss = (size_t)s * s;
+    double *buf = (double *)calloc((size_t)n * 10 + ss * 2 + 3 * (size_t)s, sizeof(double));
+    if (!buf) return ORC_ENOMEM;
+    double *y = buf, *yn = y + n, *yt = yn + n, *k[7];
+    for (int q = 0; q < 7; ++q) k[q] = yt + n + (size_t)q * n;
+    double *A = k[6] + n, *L = A + ss, *f = L + ss, *tmp = f + s, *yy = tmp + s;
+    rhs_t r;
+    int st = ORC_OK;
+    if (kind == 1) {
+        st = oracle_form_a(s, a, b, A);
+        if (!st && F) st = solve_spd(s, a, F, f, L, yy);
+        r = (rhs_t){1, s, NULL, NULL, A};
+    } else {
+        if (F)
+            for (int i = 0; i < s; ++i) f[i] = F[i] / a[i];
+        r = (rhs_t){0, s, a, b, NULL};
+    }
+    if (st) { free(buf); return st; }
+    drive_t d = {alpha, beta, omega, F ? f : NULL};
+    /* derivative of the first-order state z = (x, v) */
+#define DERIV(t_, z_, out_)                                                   \
+    do {                                                                      \
+        memcpy((out_), (z_) + s, sizeof(double) * s);                         \
+        accel_driven(&r, &d, (t_), (z_), (z_) + s, (out_) + s, tmp);          \
+    } while (0)
+    memcpy(y, x0, sizeof(double) * s);
+    memcpy(y + s, v0, sizeof(double) * s);
+    memcpy(xo, x0, sizeof(double) * s);
+    memcpy(vo, v0, sizeof(double) * s);
+    double t = 0.0;
+    DERIV(t, y, k[0]);
+    double h = 0.01 * t_end / nout;   /* first trial step; the controller adapts it */
+    int64_t acc = 0, rej = 0;
+    for (int j = 1; j <= nout && !st; ++j) {
+        const double tj = t_end * (double)j / (double)nout;
+        while (t < tj) {
+            int last = 0;
+            double hs = h;
+            if (t + hs >= tj) { hs = tj - t; last = 1; }
+            for (int i = 0; i < n; ++i) yt[i] = y[i] + hs * a21 * k[0][i];
+            DERIV(t + c2 * hs, yt, k[1]);
+            for (int i = 0; i < n; ++i) yt[i] = y[i] + hs * (a31 * k[0][i] + a32 * k[1][i]);
+            DERIV(t + c3 * hs, yt, k[2]);
+            for (int i = 0; i < n; ++i) yt[i] = y[i] + hs * (a41 * k[0][i] + a42 * k[1][i] + a43 * k[2][i]);
+            DERIV(t + c4 * hs, yt, k[3]);
+            for (int i = 0; i < n; ++i)
+                yt[i] = y[i] + hs * (a51 * k[0][i] + a52 * k[1][i] + a53 * k[2][i] + a54 * k[3][i]);
+            DERIV(t + c5 * hs, yt, k[4]);
+            for (int i = 0; i < n; ++i)
+                yt[i] = y[i] + hs * (a61 * k[0][i] + a62 * k[1][i] + a63 * k[2][i] + a64 * k[3][i] + a65 * k[4][i]);
+            DERIV(t + hs, yt, k[5]);
+            for (int i = 0; i < n; ++i)
+                yn[i] = y[i] + hs * (a71 * k[0][i] + a73 * k[2][i] + a74 * k[3][i] + a75 * k[4][i] + a76 * k[5][i]);
+            DERIV(t + hs, yn, k[6]);
+            double norm = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double err = hs * (e1 * k[0][i] + e3 * k[2][i] + e4 * k[3][i] + e5 * k[4][i] +
+                                         e6 * k[5][i] + e7 * k[6][i]);
+                const double sc = atol + rtol * fmax(fabs(y[i]), fabs(yn[i]));
+                norm += (err / sc) * (err / sc);
+            }
+            norm = sqrt(norm / n);
+            const double fac = norm > 0.0 ? fmin(5.0, fmax(0.2, 0.9 * pow(norm, -0.2))) : 5.0;
+            if (norm <= 1.0) {
+                t = last ? tj : t + hs;
+                memcpy(y, yn, sizeof(double) * n);
+                memcpy(k[0], k[6], sizeof(double) * n);   /* first stage of the next step */
+                ++acc;
+                if (!last || fac < 1.0) h = hs * fac;
+            } else {
+                h = hs * fac;
+                ++rej;
+            }
+            if (!(h > 1e-14 * t_end) || acc + rej > 100000000) { st = ORC_EINVAL; break; }
+        }
+        memcpy(xo + (size_t)j * s, y, sizeof(double) * s);
+        memcpy(vo + (size_t)j * s, y + s, sizeof(double) * s);
+    }
+#undef DERIV
+    if (stats) { stats[0] = acc; stats[1] = rej; }
+    free(buf);
+    return st;
+}

@@ -572,3 +572,156 @@ def test_pins_catch_planted_propagator_mistakes(orig, mut, tmp_path):
     hL = h * _first_order_matrix(M, K)
     T = sum(np.linalg.matrix_power(hL, j) / math.factorial(j) for j in range(5))
     assert np.abs(P - T).max() > 1e-6, "planted mistake not detected"
+
+
+# ------------------------------------------- damped and driven systems -------
+
+def _driven_case(kind, s, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "chain":
+        a, b = _random_chain(rng, s)
+        M, K = cf.chain_matrices(a, b)
+    else:
+        M, K = workloads.random_dense_system(rng, s)
+        a, b = M, K
+    w = np.sqrt(scipy.linalg.eigh(K, M, eigvals_only=True))
+    F = rng.normal(size=s) * w[-1] ** 2 * 0.1
+    x0, v0 = rng.normal(size=s), rng.normal(size=s) * w[-1]
+    return a, b, M, K, w, F, x0, v0
+
+
+@pytest.mark.parametrize("kind", ["chain", "dense"])
+def test_driven_with_no_damping_and_no_force_is_the_free_integrator(kind):
+    """alpha = beta = 0 and no force: bit for bit the free RK4 oracle."""
+    a, b, M, K, w, F, x0, v0 = _driven_case(kind, 4, 640)
+    h = 0.3 / w[-1]
+    if kind == "chain":
+        ref = oracle.chain("rk4", a[None], b[None], [h], x0[None], v0[None], 200, 20)
+        got = oracle.chain_driven(a[None], b[None], [h], 0.0, 0.0, None, 0.0, x0[None], v0[None], 200, 20)
+    else:
+        ref = oracle.dense("rk4", M, K, [h], x0[None], v0[None], 200, 20)
+        got = oracle.dense_driven(M, K, [h], 0.0, 0.0, None, 0.0, x0[None], v0[None], 200, 20)
+    for r, g in zip(ref, got):
+        np.testing.assert_array_equal(r, g)
+
+
+@pytest.mark.parametrize("kind,s", [("chain", 1), ("chain", 4), ("dense", 3)])
+def test_damped_free_matches_discrete_modal_solution(kind, s):
+    """Free damped system at h omega_max = 0.4 (the scheme visibly differs
+    from the flow) against R(hL_k)^n on every normal mode."""
+    a, b, M, K, w, F, x0, v0 = _driven_case(kind, s, 650 + s)
+    h = 0.4 / w[-1]
+    alpha, beta = 0.05 * w[0], 0.02 / w[-1]
+    n, stride = 120, 15
+    if kind == "chain":
+        xf, vf, _, _ = oracle.chain_driven(a[None], b[None], [h], alpha, beta, None, 0.0, x0[None], v0[None], n,
+                                           stride)
+    else:
+        xf, vf, _, _ = oracle.dense_driven(M, K, [h], alpha, beta, None, 0.0, x0[None], v0[None], n, stride)
+    steps = np.arange(0, n + 1, stride)
+    xr, vr = cf.rk4_damped_discrete(steps, h, M, K, alpha, beta, x0, v0)
+    assert oracle.rel_traj_err(xf, xr[:, None, :])[0] < 1e-11
+    assert oracle.rel_traj_err(vf, vr[:, None, :])[0] < 1e-11
+    exact_x, _ = cf.driven_modal_solution(steps * h, M, K, alpha, beta, None, 0.0, x0, v0)
+    assert oracle.rel_traj_err(xf, exact_x[:, None, :])[0] > 1e-6    # the scheme is visible
+
+
+@pytest.mark.parametrize("kind,s", [("chain", 2), ("chain", 5), ("dense", 4)])
+def test_driven_matches_continuous_closed_form(kind, s):
+    """Damped and driven (force near the lowest resonance), h omega_max =
+    0.004 over ~30 periods of the fastest mode: RK4's global error is ~1e-10,
+    far below any modelling mistake."""
+    a, b, M, K, w, F, x0, v0 = _driven_case(kind, s, 660 + s)
+    W = 1.1 * w[0]
+    alpha, beta = 0.1 * w[0], 0.01 / w[-1]
+    h = 0.004 / w[-1]
+    n = int(200 / (w[-1] * h))
+    stride = n // 8
+    n = stride * 8
+    if kind == "chain":
+        xf, vf, _, _ = oracle.chain_driven(a[None], b[None], [h], alpha, beta, F[None], [W], x0[None], v0[None],
+                                           n, stride)
+    else:
+        xf, vf, _, _ = oracle.dense_driven(M, K, [h], alpha, beta, F[None], [W], x0[None], v0[None], n, stride)
+    t = np.arange(0, n + 1, stride) * h
+    xr, vr = cf.driven_modal_solution(t, M, K, alpha, beta, F, W, x0, v0)
+    assert oracle.rel_traj_err(xf, xr[:, None, :])[0] < 1e-8
+    assert oracle.rel_traj_err(vf, vr[:, None, :])[0] < 1e-8
+
+
+def test_closed_form_steady_state_is_the_receptance_amplitude():
+    """Pin of the pin: once the transient has decayed, each modal coordinate
+    of the closed form oscillates with amplitude |f_k| / sqrt((w_k^2 - W^2)^2
+    + (g_k W)^2) (the textbook steady-state response)."""
+    m, k = np.array([1.0, 2.0]), np.array([300.0, 150.0])
+    M, K = cf.chain_matrices(m, k)
+    w2, Phi = scipy.linalg.eigh(K, M)
+    F, W, alpha, beta = np.array([2.0, -1.0]), 9.0, 1.5, 2e-3
+    g = alpha + beta * w2
+    T0 = 40.0 / g.min()                       # e^-20 of the transient left
+    t = T0 + np.linspace(0.0, 2 * np.pi / W, 4001)
+    x, _ = cf.driven_modal_solution(t, M, K, alpha, beta, F, W, np.ones(2), np.zeros(2))
+    q = x @ (M @ Phi)                         # modal coordinates
+    amp = 0.5 * (q.max(axis=0) - q.min(axis=0))
+    np.testing.assert_allclose(amp, cf.steady_amplitude(M, K, alpha, beta, F, W), rtol=1e-6)
+
+
+@pytest.mark.parametrize("kind", ["chain", "dense"])
+def test_dopri_reference_matches_closed_form_and_is_fifth_order(kind):
+    """The adaptive Dormand-Prince reference meets the exact solution within
+    its tolerance, and its step count grows as rtol^(-1/5) (a fifth-order
+    pair): 1e5 times tighter costs about 10 times the steps."""
+    a, b, M, K, w, F, x0, v0 = _driven_case(kind, 3, 670)
+    W, alpha, beta = 0.8 * w[0], 0.05 * w[0], 0.005 / w[-1]
+    T = 20 * 2 * np.pi / w[-1]
+    xo, vo, acc, rej = oracle.dopri_driven(kind, a, b, alpha, beta, F, W, x0, v0, T, 10, 1e-11, 1e-13)
+    t = np.linspace(0.0, T, 11)
+    xr, vr = cf.driven_modal_solution(t, M, K, alpha, beta, F, W, x0, v0)
+    assert oracle.rel_traj_err(xo[:, None, :], xr[:, None, :])[0] < 1e-8
+    assert oracle.rel_traj_err(vo[:, None, :], vr[:, None, :])[0] < 1e-8
+    _, _, acc6, _ = oracle.dopri_driven(kind, a, b, alpha, beta, F, W, x0, v0, T, 10, 1e-6, 1e-8)
+    assert 5.0 < acc / acc6 < 20.0, (acc, acc6)
+
+
+DRIVEN_MUTANTS = [
+    ("a[i] += -d->alpha * v[i] + d->beta * tmp[i]", "a[i] += d->alpha * v[i] + d->beta * tmp[i]"),  # damping sign
+    ("accel_driven(r, d, t + 0.5 * h, xt, vt, k2v, tmp)", "accel_driven(r, d, t, xt, vt, k2v, tmp)"),  # stage time
+    ("a43 = 32.0 / 9", "a43 = 31.0 / 9"),                                                            # tableau
+]
+
+
+@pytest.mark.parametrize("orig,mut", DRIVEN_MUTANTS)
+def test_pins_catch_planted_driven_mistakes(orig, mut, tmp_path):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "osc_oracle.c")).read()
+    assert src.count(orig) == 1
+    mpath = tmp_path / "mut.c"
+    mpath.write_text(src.replace(orig, mut))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(mpath), "-lm"], check=True)
+    import ctypes
+    L = ctypes.CDLL(str(lib))
+    d = ctypes.POINTER(ctypes.c_double)
+    dbl, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    L.oracle_chain_driven.argtypes = [i64, i32, d, d, d, dbl, dbl, d, d, d, d, i64, i64, d, d, d, d]
+    L.oracle_dopri_driven.argtypes = [i32, i32, d, d, dbl, dbl, d, dbl, d, d, dbl, i32, dbl, dbl, d, d,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    a, b, M, K, w, F, x0, v0 = _driven_case("chain", 3, 680)
+    W, alpha, beta = 0.9 * w[0], 0.1 * w[0], 0.01 / w[-1]
+    p = lambda arr: np.ascontiguousarray(arr, dtype=np.float64).ctypes.data_as(d)
+    keep = [np.ascontiguousarray(z, dtype=np.float64) for z in (a, b, F, x0, v0)]
+    a, b, F, x0, v0 = keep
+    h = 0.004 / w[-1]
+    n = int(100 / (w[-1] * h))
+    xe, ve = np.empty((1, 3)), np.empty((1, 3))
+    hh, WW = np.array([h]), np.array([W])
+    L.oracle_chain_driven(1, 3, p(a), p(b), p(hh), alpha, beta, p(F), p(WW), p(x0), p(v0), n, 0, None, None,
+                          p(xe), p(ve))
+    xr, vr = cf.driven_modal_solution([n * h], M, K, alpha, beta, F, W, x0, v0)
+    bad = oracle.rel_traj_err(xe, xr)[0] > 1e-8 or oracle.rel_traj_err(ve, vr)[0] > 1e-8
+    xo, vo = np.empty((2, 3)), np.empty((2, 3))
+    st = (ctypes.c_int64 * 2)()
+    r = L.oracle_dopri_driven(0, 3, p(a), p(b), alpha, beta, p(F), W, p(x0), p(v0), n * h, 1, 1e-11, 1e-13,
+                              p(xo), p(vo), st)
+    bad = bad or r != 0 or oracle.rel_traj_err(xo[1:], xr)[0] > 1e-8
+    assert bad, "planted mistake not detected"
