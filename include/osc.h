@@ -184,6 +184,28 @@ osc_status osc_energy(osc_sys *sys, const void *x, const void *v, double *E);
 osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double *Q);
 
 /*
+ * osc_set_excitation -- damp and drive every instance of the handle: eq. (1)
+ * with Rayleigh damping C = alpha M + beta K and a harmonic force,
+ *     M x'' + C x' + K x = F cos(Omega t),
+ * integrated by classic RK4 on the first-order form of section 3 (stages at
+ * t_n, t_n + dt/2, t_n + dt/2, t_n + dt; t_n = n dt from the integer step).
+ * alpha, beta >= 0 (same for every instance).  F: forces [batch][s] (host or
+ * device per mem), or NULL for no force; Omega: [batch] frequencies (rad per
+ * unit time), required with F.  Dense systems take f = M^-1 F on the GPU (FP64,
+ * by the Cholesky factor of M).  alpha = beta = 0 and F = NULL make the
+ * handle free again.  Afterwards osc_integrate (and osc_integrate_static) run
+ * the damped / driven integrator (one workgroup per instance; s <= 2048);
+ * osc_integrate_plain and the propagator modes return OSC_ENOTSUP; osc_energy
+ * still returns 1/2 v^T M v + 1/2 x^T K x (no longer conserved).
+ * OSC_ENOTSUP for a Verlet handle (the velocity-dependent force would make the
+ * scheme implicit).  OSC_EUNSTABLE when dt * max(omega_max, alpha + beta
+ * omega_max^2) exceeds 2.5: every mode's |lambda| is at most that, and RK4's
+ * stability region holds the left half-disk of radius 2.6156.  Synchronous.
+ */
+osc_status osc_set_excitation(osc_sys *sys, double alpha, double beta, const double *F, const double *Omega,
+                              osc_mem mem);
+
+/*
  * osc_propagator -- the matrix of k steps of the handle's scheme.  For
  * eq. (1) the first-order system of section 3 is y' = L y with the constant
  * L = [[0, I], [-A, 0]], y = (x, v), so k steps of either scheme are one

@@ -68,7 +68,8 @@ osc_status copy_in(void *dst, const void *src, size_t bytes, osc_mem where, hipS
 void release(osc_sys *s) {
     if (!s) return;
     for (void *p : {(void *)s->m, (void *)s->k, (void *)s->h, s->coef, (void *)s->flag, s->plain_state,
-                    (void *)s->A, s->Bh, s->Bl, s->F1, s->F2, s->state, s->split_scratch})
+                    (void *)s->A, s->Bh, s->Bl, s->F1, s->F2, s->state, s->split_scratch, (void *)s->force,
+                    (void *)s->omega})
         pool_free(p);
     pool_free(s->mfma_items);
     if (s->split_graph) (void)hipGraphExecDestroy(s->split_graph);
@@ -577,6 +578,37 @@ osc_status integrate_prop_step(osc_sys *s, const void *x0, const void *v0, int64
                       [&](const ChainLaunch<T> &c) { return prop_step_launch<T>(c, s->method, s->stream); });
 }
 
+// Damped and driven systems (osc_set_excitation): stage-form RK4, one
+// workgroup per instance.
+template <typename T>
+osc_status integrate_driven(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
+                            void *xf, void *vf, void *xe, void *ve) {
+    if (s->propagator)
+        return fail(OSC_ENOTSUP, "the propagator modes take free (undamped, undriven) systems");
+    DrivenLaunch<T> a{};
+    a.kind = s->kind;
+    a.batch = s->batch;
+    a.s = s->s;
+    a.shared = s->kind == OSC_DENSE ? s->shared : 0;
+    if (s->kind == OSC_CHAIN) a.c = coef_of<T>(s);
+    a.Bh = static_cast<const T *>(s->Bh);
+    a.Bl = static_cast<const T *>(s->Bl);
+    a.h = s->h;
+    a.alpha = s->alpha;
+    a.beta = s->beta;
+    a.f = s->force;
+    a.omega = s->omega;
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.out_stride = out_stride;
+    a.xf = static_cast<T *>(xf);
+    a.vf = static_cast<T *>(vf);
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.nonfinite = s->flag;
+    return run_chunks(s, a, nsteps, [&](const DrivenLaunch<T> &c) { return driven_launch<T>(c, s->stream); });
+}
+
 }  // namespace
 
 template <typename T>
@@ -740,6 +772,9 @@ static osc_status integrate_checks(osc_sys *s, const void *x0, const void *v0, i
 
 static osc_status integrate_any(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
                                 void *xf, void *vf, void *xe, void *ve) {
+    if (s->driven)
+        return s->prec == OSC_F32 ? integrate_driven<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
+                                  : integrate_driven<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
     if (s->propagator == 1)
         return s->prec == OSC_F32 ? integrate_jump<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                                   : integrate_jump<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
@@ -768,13 +803,15 @@ osc_status osc_integrate_static(osc_sys *s, const void *x0, const void *v0, int6
     if (r || s->batch == 0) return r;
     // device memory the run needs beyond its inputs and outputs
     size_t need_state = 0, need_split = 0;
-    if (s->propagator == 1 && !propagator_small(s->s))
+    if (s->propagator == 1 && !propagator_small(s->s) && !s->driven)
         return fail(OSC_ENOTSUP, "osc_integrate_static: frame jumps of systems with s > 2 form their matrix powers "
                                  "in per-call buffers; use osc_integrate");
     if (s->propagator == 0 && s->kind == OSC_DENSE && use_mfma(s) && !s->shared)
         return fail(OSC_ENOTSUP, "osc_integrate_static: per-instance operators on the matrix cores take a work "
                                  "list built per call; use osc_integrate");
-    if (s->propagator == 1) {
+    if (s->driven) {
+        if (s->steps_per_launch > 0 && nsteps > s->steps_per_launch) need_state = state_bytes(s);
+    } else if (s->propagator == 1) {
         // one kernel per call, no scratch
     } else if (s->propagator == 0 && s->kind == OSC_DENSE && !use_mfma(s) && use_split(s)) {
         need_state = state_bytes(s);
@@ -803,6 +840,7 @@ osc_status osc_integrate_static(osc_sys *s, const void *x0, const void *v0, int6
 osc_status osc_integrate_plain(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, void *xe, void *ve) {
     g_last_error.clear();
     if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    if (s->driven) return fail(OSC_ENOTSUP, "the plain baseline takes free (undamped, undriven) systems");
     if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
     if (s->batch == 0) return OSC_OK;
     if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
@@ -838,6 +876,67 @@ osc_status osc_energy(osc_sys *s, const void *x, const void *v, double *E) { ret
 
 osc_status osc_shadow_energy(osc_sys *s, const void *x, const void *v, double *Q) {
     return energy_common(s, x, v, Q, true);
+}
+
+osc_status osc_set_excitation(osc_sys *s, double alpha, double beta, const double *F, const double *Omega,
+                              osc_mem mem) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    if (!(alpha >= 0.0 && std::isfinite(alpha)) || !(beta >= 0.0 && std::isfinite(beta)))
+        return fail(OSC_EINVAL, "alpha and beta must be finite and >= 0");
+    if (mem != OSC_MEM_HOST && mem != OSC_MEM_DEVICE) return fail(OSC_EINVAL, "unknown mem");
+    if (F && !Omega) return fail(OSC_EINVAL, "a force needs its frequencies Omega");
+    const bool on = alpha != 0.0 || beta != 0.0 || F != nullptr;
+    if (on && s->method != OSC_RK4)
+        return fail(OSC_ENOTSUP, "damped / driven systems are integrated by RK4 only");
+    const hipStream_t st = s->stream;
+    const int64_t nh = s->kind == OSC_CHAIN ? s->batch : s->nsys;
+    if ((alpha != 0.0 || beta != 0.0) && nh > 0) {
+        // per mode |lambda| <= max(omega, alpha + beta omega^2); RK4's
+        // stability region holds the left half-disk of radius 2.6156
+        std::vector<double> hh((size_t)nh);
+        OSC_HIP(hipMemcpyAsync(hh.data(), s->h, nh * sizeof(double), hipMemcpyDeviceToHost, st));
+        OSC_HIP(hipStreamSynchronize(st));
+        const double hmin = *std::min_element(hh.begin(), hh.end()), hmax = *std::max_element(hh.begin(), hh.end());
+        const double th = s->theta_max, gh = alpha * hmax + beta * th * th / hmin;
+        const double lim = 2.5;
+        if (!(std::max(th, gh) <= lim))
+            return fail(OSC_EUNSTABLE, "dt * max(omega_max, alpha + beta omega_max^2) = " +
+                                           std::to_string(std::max(th, gh)) + " exceeds " + std::to_string(lim));
+    }
+    pool_free(s->force);
+    pool_free(s->omega);
+    s->force = s->omega = nullptr;
+    s->driven = false;
+    if (F && s->batch > 0) {
+        const size_t n = (size_t)s->batch * s->s;
+        DevBuf Fdev, flag;
+        s->force = static_cast<double *>(pool_alloc(n * sizeof(double)));
+        s->omega = static_cast<double *>(pool_alloc((size_t)s->batch * sizeof(double)));
+        flag.p = pool_alloc(64);
+        const double *Fp = F;
+        if (mem == OSC_MEM_HOST) {
+            Fdev.p = pool_alloc(n * sizeof(double));
+            if (Fdev.p) OSC_HIP(hipMemcpyAsync(Fdev.p, F, n * sizeof(double), hipMemcpyHostToDevice, st));
+            Fp = static_cast<const double *>(Fdev.p);
+        }
+        if (!s->force || !s->omega || !flag.p || !Fp) {
+            OSC_HIP(hipStreamSynchronize(st));
+            return fail(OSC_ENOMEM, "device memory exhausted for the force");
+        }
+        osc_status r = copy_in(s->omega, Omega, (size_t)s->batch * sizeof(double), mem, st);
+        if (r) return r;
+        OSC_HIP(hipMemsetAsync(flag.p, 0, 64, st));
+        r = s->kind == OSC_CHAIN ? chain_force((int64_t)n, Fp, s->m, s->force, st)
+                                 : dense_force(s->s, s->nsys, s->batch, s->m, Fp, s->force,
+                                               static_cast<int *>(flag.p), st);
+        if (r) return r;
+        OSC_HIP(hipStreamSynchronize(st));   // the staged force is released below
+    }
+    s->alpha = alpha;
+    s->beta = beta;
+    s->driven = on;
+    return OSC_OK;
 }
 
 osc_status osc_propagator(osc_sys *s, int64_t k, double *P) {

@@ -295,6 +295,37 @@ osc_status propagator_jump(const PropArgs &a, int s, const PropRun<T> &run, hipS
 template <typename T>
 osc_status prop_step_launch(const ChainLaunch<T> &a, int method, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// damped and driven systems (driven.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct DrivenLaunch {
+    int kind;                  // OSC_CHAIN / OSC_DENSE
+    int64_t batch;
+    int32_t s;
+    int32_t shared;            // dense: one operator for every instance
+    int32_t nbuf;              // LDS stage buffers (set by driven_launch)
+    ChainCoef<T> c;            // chains
+    const T *Bh, *Bl;          // dense: h^2 A column-major, [nsys][s][s]
+    const double *h;           // chains [batch], dense [nsys]
+    double alpha, beta;        // Rayleigh damping C = alpha M + beta K
+    const double *f;           // [batch][s] M^-1 F, or nullptr (no force)
+    const double *omega;       // [batch] force frequency
+    const T *x0, *v0;
+    T *state;                  // [4][batch][s] as for chains
+    int64_t nsteps, n0, out_stride;
+    T *xf, *vf, *xe, *ve;
+    int *nonfinite;
+    int load_mode, store_mode;
+};
+template <typename T>
+osc_status driven_launch(const DrivenLaunch<T> &a, hipStream_t st);
+// f = F / m (chains, [n] elements)
+osc_status chain_force(int64_t n, const double *F, const double *m, double *f, hipStream_t st);
+// f_b = M^-1 F_b for dense systems (M^-1 by the Cholesky formation with K = I)
+osc_status dense_force(int s, int64_t nsys, int64_t batch, const double *M, const double *F, double *f,
+                       int *notspd, hipStream_t st);
+
 // runtime helpers shared by the server (api.hip)
 template <typename T>
 ChainCoef<T> chain_coef(const osc_sys *s);
@@ -351,6 +382,11 @@ struct osc_sys {
     // scratch instead of the handle's own (allocated on demand), and no graph
     // is captured
     int propagator = 0;                  // OSC_CFG_PROPAGATOR: 0 off, 1 frame jumps, 2 per-step (chains s <= 2)
+    // osc_set_excitation: Rayleigh damping and harmonic force (RK4 only)
+    bool driven = false;
+    double alpha = 0.0, beta = 0.0;
+    double *force = nullptr;             // [batch][s] M^-1 F (device), or nullptr
+    double *omega = nullptr;             // [batch] (device)
     bool static_call = false;
     void *scratch_state = nullptr;
     void *scratch_split = nullptr;

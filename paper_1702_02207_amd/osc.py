@@ -80,6 +80,7 @@ def load():
         "osc_sync": (i32, [vp]),
         "osc_dense_operator": (i32, [vp, vp]),
         "osc_propagator": (i32, [vp, i64, vp]),
+        "osc_set_excitation": (i32, [vp, ctypes.c_double, ctypes.c_double, vp, vp, i32]),
         "osc_set_config": (i32, [vp, i32, i64]),
         "osc_autotune": (i32, [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]),
         "osc_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
@@ -274,6 +275,39 @@ class System:
         chosen = ctypes.c_int64(0)
         _check(load().osc_autotune(self.handle, _dptr(x0), _dptr(v0), int(probe_steps), ctypes.byref(chosen)))
         return chosen.value
+
+    def set_excitation(self, alpha: float = 0.0, beta: float = 0.0, F=None, omega=None):
+        """osc_set_excitation: Rayleigh damping alpha M + beta K and a force
+        F cos(omega t).  F: [batch, s] float64 (numpy or CUDA tensor) or None;
+        omega: [batch] (or a scalar for every instance)."""
+        import torch
+        if self.handle is None:
+            raise ValueError("the system has not been created (call create())")
+        keep = []
+        Fp = Wp = None
+        mem = MEM_HOST
+        if F is not None:
+            if omega is None:
+                raise ValueError("a force needs omega")
+            if isinstance(F, torch.Tensor):
+                if not F.is_cuda or F.dtype != torch.float64 or tuple(F.shape) != (self.batch, self.s):
+                    raise ValueError(f"F must be a CUDA float64 tensor of shape {(self.batch, self.s)}")
+                F = F.contiguous()
+                W = torch.as_tensor(np.broadcast_to(np.atleast_1d(np.asarray(omega, dtype=np.float64)),
+                                                    (self.batch,)).copy(), device=F.device)
+                mem = MEM_DEVICE
+                keep += [F, W]
+                Fp, Wp = F.data_ptr(), W.data_ptr()
+            else:
+                F = np.ascontiguousarray(F, dtype=np.float64)
+                if F.shape != (self.batch, self.s):
+                    raise ValueError(f"F has shape {F.shape}, expected {(self.batch, self.s)}")
+                W = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(np.asarray(omega, dtype=np.float64)),
+                                                         (self.batch,)))
+                keep += [F, W]
+                Fp, Wp = F.ctypes.data, W.ctypes.data
+        _check(load().osc_set_excitation(self.handle, float(alpha), float(beta), Fp, Wp, mem))
+        return self
 
     def propagator(self, k: int = 1):
         """osc_propagator: the FP64 matrix of k steps on (x, v), a new device
