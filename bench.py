@@ -26,8 +26,10 @@ method (classic stage form: RK4 48 flop per DOF-step for chains, 44 for the
 two-mass system; Verlet 10), with the implementation's own count beside it;
 the FP64 oracle timed on the host cores on a bounded sample (instance 0, the
 last instance and seeded others); the relative trajectory error of that
-sample against the oracle; and a served stream (p50/p99 latency, per kind,
-and DOF-steps/s of 200 requests at half the measured saturation rate).
+sample against the oracle; a served stream (p50/p99 latency, per kind,
+and DOF-steps/s of 200 requests at half the measured saturation rate); and
+real-time stepping of the paper's system (one step per 20 us / 100 us / 1 ms
+period: release-to-result latency, jitter, missed deadlines).
 """
 from __future__ import annotations
 
@@ -391,6 +393,32 @@ def serve_pass(args, method="rk4", prec="f32"):
     }
 
 
+def realtime_pass(args):
+    """The paper's two-mass system (eq. (3), FP64, RK4, dt = 1e-5) stepped in
+    real time: one step per wall-clock period (osc_rt_run), the latency from
+    each release to the result being ready on the host."""
+    import torch
+    from paper_1702_02207_amd import osc, workloads
+    w = workloads.c1_paper_two_mass(nsteps=1, out_stride=1)
+    x0 = torch.as_tensor(w.x0, dtype=torch.float64, device="cuda:0")
+    v0 = torch.as_tensor(w.v0, dtype=torch.float64, device="cuda:0")
+    sysm = osc.System("chain", "rk4", "f64", w.m, w.k, w.dt).create()
+    out = {"workload": "paper's two-mass system eq. (3), FP64 RK4, one step per period",
+           "ticks_per_period": args.rt_ticks, "periods": []}
+    try:
+        for period in (20e-6, 100e-6, 1e-3):
+            _log(f"[bench] real-time: period {period * 1e6:.0f} us, {args.rt_ticks} ticks")
+            with osc.Realtime(sysm, x0, v0, 1) as rt:
+                _, _, _, st = rt.run(period, args.rt_ticks, frames=False)
+            out["periods"].append({"period_s": period, "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
+                                   "max_latency_s": st["max_s"], "jitter_s": st["jitter_s"],
+                                   "missed": int(st["missed"]), "gpu_p50_s": st["gpu_p50_s"],
+                                   "launch_p99_s": st["launch_p99_s"]})
+    finally:
+        sysm.close()
+    return out
+
+
 def bench_serve(args, spec):
     sv = serve_pass(args, spec["method"], spec["prec"])
     return {
@@ -415,6 +443,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="0 = workload default (CPU_SAMPLE)")
     ap.add_argument("--no-serve", action="store_true", help="leave the served-stream pass out of the line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-realtime", action="store_true", help="leave the real-time stepping pass out of the line")
+    ap.add_argument("--rt-ticks", type=int, default=1000, help="real-time pass: periods per tested period length")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the stream")
     ap.add_argument("--qps", type=float, default=0.0, help="c5: arrival rate (0 = load x saturation)")
@@ -447,6 +477,8 @@ def main():
         out = bench_batched(args, args.workload, spec)
         if not args.no_serve:
             out["serving"] = serve_pass(args)
+        if not args.no_realtime:
+            out["realtime"] = realtime_pass(args)
     for r in (out.get("serving") or {}), (out.get("serving") or {}).get("saturation", {}):
         r.pop("results", None)
     print(json.dumps(out), flush=True)

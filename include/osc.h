@@ -298,6 +298,61 @@ const char *osc_last_error(void);
 int osc_abi_version(void);
 
 /* ------------------------------------------------------------------------ */
+/* Real-time periodic stepping.                                              */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper proposes the oscillator model as a time-critical workload for
+ * hardware- and software-in-the-loop simulation and as a benchmark of the
+ * delay of parallel systems and of periodic hard-deadline threads
+ * (introduction, section 5).  A real-time stepper holds one handle's state on
+ * the device and advances it by one tick (steps_per_tick steps, one kernel
+ * launch) at a time.  A tick continues the handle's integration from the
+ * global step count with its compensation terms, so the states after the
+ * ticks are bit for bit the frames of one osc_integrate call with
+ * out_stride = steps_per_tick.  Supported: chains, dense systems on the VALU
+ * and shared-operator MFMA paths, damped / driven systems, the per-step
+ * propagator; OSC_ENOTSUP for frame jumps, the split dense path and
+ * per-instance dense operators on the matrix cores.  The handle must outlive
+ * the stepper and not be integrated in between.
+ */
+typedef struct osc_rt osc_rt;
+
+/* osc_rt_create -- a stepper at step 0 from (x0, v0) (device [batch][s], copied). */
+osc_status osc_rt_create(osc_sys *sys, const void *x0, const void *v0, int64_t steps_per_tick, osc_rt **out);
+
+/* osc_rt_tick -- advance one tick, asynchronously on the handle's stream; the
+ * new state goes to x_out, v_out (device [batch][s]; NULL: kept internally). */
+osc_status osc_rt_tick(osc_rt *rt, void *x_out, void *v_out);
+
+/* osc_rt_steps -- steps taken so far (-1 for NULL). */
+int64_t osc_rt_steps(const osc_rt *rt);
+
+typedef struct osc_rt_stats {
+    int64_t ticks;         /* periods run */
+    int64_t missed;        /* ticks whose result was ready only after the next release */
+    double p50_s, p99_s, max_s, mean_s;   /* latency: release time -> result ready (host clock) */
+    double jitter_s;       /* standard deviation of the latency */
+    double launch_p99_s;   /* release -> tick enqueued, 99th percentile */
+    double gpu_p50_s;      /* device time of a tick (events around its launch), median */
+} osc_rt_stats;
+
+/*
+ * osc_rt_run -- the periodic loop: nticks periods of period_s seconds (0 <
+ * period_s < 60) on the host's steady clock.  At each release time one tick
+ * is enqueued and its completion event polled (at most max(10 s, 100 periods)
+ * per tick: OSC_ETIMEOUT beyond); the latency is release -> completion seen
+ * by the host, and a tick misses its deadline when that exceeds one period.
+ * x_frames, v_frames: device [nticks][batch][s] for the state after each tick,
+ * or NULL; latencies: host double [nticks] or NULL; stats may be NULL.
+ * Blocks for about nticks * period_s.
+ */
+osc_status osc_rt_run(osc_rt *rt, double period_s, int64_t nticks, void *x_frames, void *v_frames,
+                      double *latencies, osc_rt_stats *stats);
+
+/* osc_rt_destroy -- release the stepper (waits for its queued ticks).  NULL is a no-op. */
+void osc_rt_destroy(osc_rt *rt);
+
+/* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of single-instance integration requests.     */
 /* ------------------------------------------------------------------------ */
 /*

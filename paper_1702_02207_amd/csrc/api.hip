@@ -109,6 +109,18 @@ void set_sigma(DenseMfmaLaunch &a, osc_sys *s) {
 // the compensated state through device memory between launches.
 template <typename L, typename F>
 osc_status run_chunks(osc_sys *s, L base, int64_t nsteps, F &&launch) {
+    if (s->rt_chunk) {
+        // one real-time tick
+        osc_status r = ensure_state(s);
+        if (r) return r;
+        base.n0 = s->rt_n0;
+        base.nsteps = nsteps;
+        base.load_mode = s->rt_load;
+        base.store_mode = STORE_STATE | STORE_USER;
+        base.state = static_cast<decltype(base.state)>(state_buf(s));
+        set_sigma(base, s);
+        return launch(base);
+    }
     const int64_t chunk = s->steps_per_launch > 0 ? s->steps_per_launch : nsteps;
     if (nsteps <= chunk) {
         base.n0 = 0;
@@ -977,3 +989,29 @@ void osc_destroy(osc_sys *s) {
 }
 
 }  // extern "C"
+
+namespace osc {
+
+osc_status sys_rt_supported(const osc_sys *s) {
+    if (s->propagator == 1) return fail(OSC_ENOTSUP, "real-time stepping takes the stepping integrators, not frame jumps");
+    if (s->kind == OSC_DENSE && !s->driven) {
+        if (use_mfma(s) && !s->shared)
+            return fail(OSC_ENOTSUP, "real-time stepping: per-instance operators on the matrix cores are not supported");
+        if (!use_mfma(s) && use_split(s))
+            return fail(OSC_ENOTSUP, "real-time stepping: the split dense path (large s, few instances) is not supported");
+    }
+    return OSC_OK;
+}
+
+osc_status sys_rt_tick(osc_sys *s, const void *x0, const void *v0, int64_t n0, int64_t k, void *xe, void *ve) {
+    osc_status r = sys_rt_supported(s);
+    if (r) return r;
+    s->rt_chunk = true;
+    s->rt_n0 = n0;
+    s->rt_load = n0 == 0 ? LOAD_USER : LOAD_STATE;
+    r = integrate_any(s, x0, v0, k, 0, nullptr, nullptr, xe, ve);
+    s->rt_chunk = false;
+    return r;
+}
+
+}  // namespace osc

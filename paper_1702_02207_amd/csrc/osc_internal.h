@@ -336,6 +336,11 @@ osc_status sys_ensure_split_scratch(osc_sys *s);
 template <typename T>
 void split_launch_base(osc_sys *s, DenseSplitLaunch<T> &a);
 void autotune_apply_cached(osc_sys *s);   // autotune.hip
+// One real-time tick: k steps from global step n0 (LOAD_USER from x0, v0 when
+// n0 == 0, else the held state), the new state stored back and written to
+// (xe, ve).  OSC_ENOTSUP for paths that keep no per-launch state planes.
+osc_status sys_rt_tick(osc_sys *s, const void *x0, const void *v0, int64_t n0, int64_t k, void *xe, void *ve);
+osc_status sys_rt_supported(const osc_sys *s);
 
 }  // namespace osc
 
@@ -387,6 +392,12 @@ struct osc_sys {
     double alpha = 0.0, beta = 0.0;
     double *force = nullptr;             // [batch][s] M^-1 F (device), or nullptr
     double *omega = nullptr;             // [batch] (device)
+    // real-time stepping (osc_rt_tick): the next integration is one launch
+    // from global step rt_n0 that loads the held state (or the given initial
+    // state when rt_load == LOAD_USER) and stores it back beside the output
+    bool rt_chunk = false;
+    int64_t rt_n0 = 0;
+    int rt_load = 0;
     bool static_call = false;
     void *scratch_state = nullptr;
     void *scratch_split = nullptr;

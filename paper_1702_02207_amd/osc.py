@@ -34,6 +34,12 @@ class OscError(RuntimeError):
         self.status = status
 
 
+class RtStats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("missed", ctypes.c_int64), ("p50_s", ctypes.c_double),
+                ("p99_s", ctypes.c_double), ("max_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("jitter_s", ctypes.c_double), ("launch_p99_s", ctypes.c_double), ("gpu_p50_s", ctypes.c_double)]
+
+
 class Desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("method", ctypes.c_int), ("prec", ctypes.c_int),
                 ("s", ctypes.c_int32), ("batch", ctypes.c_int64), ("shared", ctypes.c_int32),
@@ -81,6 +87,11 @@ def load():
         "osc_dense_operator": (i32, [vp, vp]),
         "osc_propagator": (i32, [vp, i64, vp]),
         "osc_set_excitation": (i32, [vp, ctypes.c_double, ctypes.c_double, vp, vp, i32]),
+        "osc_rt_create": (i32, [vp, vp, vp, i64, ctypes.POINTER(vp)]),
+        "osc_rt_tick": (i32, [vp, vp, vp]),
+        "osc_rt_steps": (i64, [vp]),
+        "osc_rt_run": (i32, [vp, ctypes.c_double, i64, vp, vp, vp, ctypes.POINTER(RtStats)]),
+        "osc_rt_destroy": (None, [vp]),
         "osc_set_config": (i32, [vp, i32, i64]),
         "osc_autotune": (i32, [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]),
         "osc_server_create": (i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
@@ -337,6 +348,68 @@ class System:
         if self.handle is not None:
             load().osc_destroy(self.handle)
             self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Realtime:
+    """Real-time periodic stepping of one created System (osc_rt_*): the
+    state stays on the device; each tick advances steps_per_tick steps."""
+
+    def __init__(self, system: "System", x0, v0, steps_per_tick: int = 1):
+        self.system = system
+        x0, v0 = system._state(x0, "x0"), system._state(v0, "v0")
+        if steps_per_tick < 1:
+            raise ValueError("steps_per_tick must be >= 1")
+        h = ctypes.c_void_p()
+        _check(load().osc_rt_create(system.handle, _dptr(x0), _dptr(v0), int(steps_per_tick), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def steps(self) -> int:
+        return int(load().osc_rt_steps(self.handle))
+
+    def tick(self, out=None):
+        """One tick; returns (x, v) device tensors of the new state."""
+        import torch
+        sysm = self.system
+        if out is None:
+            out = (torch.empty((sysm.batch, sysm.s), dtype=sysm.dtype, device="cuda"),
+                   torch.empty((sysm.batch, sysm.s), dtype=sysm.dtype, device="cuda"))
+        x, v = (sysm._state(t, "out") for t in out)
+        _check(load().osc_rt_tick(self.handle, _dptr(x), _dptr(v)))
+        return x, v
+
+    def run(self, period_s: float, nticks: int, frames: bool = True):
+        """osc_rt_run: returns (x_frames, v_frames, latencies [s], stats dict);
+        frames are the states after each tick, [nticks, batch, s]."""
+        import torch
+        sysm = self.system
+        xf = vf = None
+        if frames and nticks > 0:
+            xf = torch.empty((nticks, sysm.batch, sysm.s), dtype=sysm.dtype, device="cuda")
+            vf = torch.empty_like(xf)
+        lat = np.zeros(max(nticks, 1))
+        st = RtStats()
+        _check(load().osc_rt_run(self.handle, float(period_s), int(nticks), _dptr(xf), _dptr(vf),
+                                 lat.ctypes.data, ctypes.byref(st)))
+        stats = {name: getattr(st, name) for name, _ in RtStats._fields_}
+        return xf, vf, lat[:nticks], stats
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().osc_rt_destroy(self.handle)
+        self.handle = None
 
     def __enter__(self):
         return self
