@@ -63,13 +63,18 @@ DENSE_PRODUCTS = {"rk4": 4, "verlet": 1}
 DENSE_HW_TERMS = {"rk4": 7, "verlet": 3}     # MFMA products per step with the FP16 splits
 
 # oracle sample sizes (instance 0, the last instance and seeded others)
-CPU_SAMPLE = {"c1": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c4": 256,
-              "c4v": 256, "c4j": 256}
+CPU_SAMPLE = {"c1": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c3d": 32,
+              "c4": 256, "c4v": 256, "c4j": 256}
 # the per-step propagator's own count for two-mass RK4 at FP32: per DOF, dx
 # from the low parts, the w terms and the high parts of one row of the 4x4
 # step matrix (6 FMA) plus w (1 add), dw likewise (6 FMA), two compensated
 # sums (2 adds) and two state reads (2 adds)
 IMPL_PROP_STEP_FLOPS = 29
+# classic stage-form RK4 of the damped, driven chain (FMA = 2): per stage two
+# stencil products (B X, B W: 5 flop each), the slope -B X - a W - b B W + f c
+# (6) and the next stage's arguments (4); four stages less the first one's
+# arguments, plus the weighted combination (9)
+ALG_DRIVEN_CHAIN_FLOPS = 85
 
 WORKLOADS = {
     "c1": dict(kind="chain", method="rk4", prec="f64",
@@ -95,6 +100,9 @@ WORKLOADS = {
     "c4j": dict(kind="dense", method="rk4", prec="f32", propagator=1,
                 desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, frames every 1000 steps "
                      "by powers of the step matrix (FP64 matrix cores, FP32 in/out)"),
+    "c3d": dict(kind="chain", method="rk4", prec="f32", driven=True,
+                desc="fixed-free spring chain: 4096 instances, s=1024, 1e4 RK4 steps, FP32, Rayleigh damping "
+                     "(alpha=0.05, beta=1e-5) and a harmonic force per chain"),
     "c5": dict(kind="serve", method="rk4", prec="f32",
                desc="served stream: chains and dense SPD systems, s LogU[2,2048], nsteps LogU[1e3,1e5], FP32"),
 }
@@ -111,6 +119,10 @@ def make_workload(name):
     if name.startswith("c2"):
         w = workloads.c2_two_dof_ensemble()
         w.out_stride = 100 if name == "c2j" else w.nsteps
+        return w
+    if name == "c3d":
+        w, ex = workloads.c3_driven_chain()
+        w.excitation = ex
         return w
     if name.startswith("c3"):
         w = workloads.c3_spring_chain()
@@ -171,7 +183,11 @@ def cpu_baseline(w, kind, method, prec, idx):
         v0 = v0.astype(np.float32).astype(np.float64)
     threads = host_threads()
     t0 = time.perf_counter()
-    if kind == "chain":
+    if getattr(w, "excitation", None) is not None:
+        ex = w.excitation.subset(idx)
+        xf, vf, _, _ = oracle.chain_driven(sub.m, sub.k, sub.dt, ex.alpha, ex.beta, ex.F, ex.omega, x0, v0,
+                                           w.nsteps, w.out_stride)
+    elif kind == "chain":
         xf, vf, _, _ = oracle.chain(method, sub.m, sub.k, sub.dt, x0, v0, w.nsteps, w.out_stride)
     else:
         xf, vf, _, _ = oracle.dense(method, sub.M, sub.K, sub.dt, x0, v0, w.nsteps, w.out_stride,
@@ -242,6 +258,9 @@ def bench_batched(args, name, spec):
             sysm = osc.System("dense", method, prec, P1, P2, P3, shared=True, batch=w.batch, stream=stream).create()
         if mode:
             sysm.set_config(osc.CFG_PROPAGATOR, mode)
+        if spec.get("driven"):
+            ex = w.excitation
+            sysm.set_excitation(ex.alpha, ex.beta, ex.F, ex.omega)
         return sysm
 
     def one_step(record):
@@ -277,6 +296,12 @@ def bench_batched(args, name, spec):
     kavg = float(np.mean(kern_ms)) * 1e-3
     if mode == 1:
         roofline = jump_roofline(w, kind, kavg)
+    elif spec.get("driven"):
+        fpd = ALG_DRIVEN_CHAIN_FLOPS
+        achieved = fpd * dof_steps / kavg / 1e12
+        roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK["fp32"], unit="TFLOP/s",
+                        frac=round(achieved / PEAK["fp32"], 4), traffic=None, kernel="driven_kernel",
+                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd)
     elif kind == "chain":
         fpd = (ALG_CHAIN2_FLOPS if w.s == 2 else ALG_CHAIN_FLOPS)[method]
         impl = IMPL_PROP_STEP_FLOPS if mode == 2 else IMPL_CHAIN_FLOPS[(method, prec)]
@@ -310,7 +335,7 @@ def bench_batched(args, name, spec):
         "roofline": roofline,
     }
 
-    if not args.no_plain:
+    if not args.no_plain and not spec.get("driven"):
         pn = min(args.plain_instances, w.batch)
         psteps = args.plain_steps or w.nsteps
         sub = w.subset(np.arange(pn))

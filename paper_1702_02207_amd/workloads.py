@@ -189,6 +189,30 @@ def c3_spring_chain(batch: int = 4096, s: int = 1024, nsteps: int = 100_000,
     return ChainBatch(m, k, dt, x0, np.zeros_like(x0), nsteps, out_stride)
 
 
+@dataclasses.dataclass
+class Excitation:
+    """Rayleigh damping alpha M + beta K and a force F cos(omega t) per instance."""
+    alpha: float
+    beta: float
+    F: np.ndarray          # [batch, s] float64
+    omega: np.ndarray      # [batch] float64
+
+    def subset(self, idx) -> "Excitation":
+        idx = np.asarray(idx)
+        return Excitation(self.alpha, self.beta, self.F[idx].copy(), self.omega[idx].copy())
+
+
+def c3_driven_chain(batch: int = 4096, s: int = 1024, nsteps: int = 10_000, out_stride: int = 1000):
+    """The C3 chains (same masses, springs, x0) with light Rayleigh damping
+    (alpha = 0.05, beta = 1e-5), forces F ~ N(0, 10^2) per DOF and one
+    frequency omega ~ U[1, 100] per chain.  Returns (ChainBatch, Excitation)."""
+    w = c3_spring_chain(batch=batch, s=s, nsteps=nsteps, out_stride=out_stride)
+    rng = _rng(2, salt=1)
+    F = rng.normal(0.0, 10.0, (4096, s))[:batch]
+    omega = rng.uniform(1.0, 100.0, 4096)[:batch]
+    return w, Excitation(0.05, 1e-5, F.copy(), omega.copy())
+
+
 def haar_orthogonal(rng, s: int) -> np.ndarray:
     g = rng.normal(0.0, 1.0, (s, s))
     q, r = np.linalg.qr(g)
