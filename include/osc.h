@@ -240,6 +240,8 @@ osc_status osc_dense_operator(osc_sys *sys, double *A);
  *                             instance (any s), 2 MFMA (FP32, shared operator,
  *                             s <= 256), 3 split (each step three kernels over
  *                             many workgroups; for few instances of large s).
+ *                             Damped / driven chains: 0 automatic (registers
+ *                             for s <= 1024), 1 one workgroup per instance.
  *   OSC_CFG_STEPS_PER_LAUNCH  maximum time steps per kernel launch (0 = the
  *                             whole run).  The state between launches keeps its
  *                             compensation terms, so chunked and unchunked runs

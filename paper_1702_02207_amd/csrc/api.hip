@@ -618,6 +618,7 @@ osc_status integrate_driven(osc_sys *s, const void *x0, const void *v0, int64_t 
     a.xe = static_cast<T *>(xe);
     a.ve = static_cast<T *>(ve);
     a.nonfinite = s->flag;
+    a.force_workgroup = s->dense_kernel == 1 ? 1 : 0;
     return run_chunks(s, a, nsteps, [&](const DrivenLaunch<T> &c) { return driven_launch<T>(c, s->stream); });
 }
 
@@ -747,6 +748,11 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
             return fail(OSC_ENOTSUP, "no kernel built for this layout");
         }
         case OSC_CFG_DENSE_KERNEL:
+            if (s->kind == OSC_CHAIN && (value == 0 || value == 1)) {
+                // damped / driven chains: 1 = the one-workgroup-per-instance kernel
+                s->dense_kernel = (int)value;
+                return OSC_OK;
+            }
             if (s->kind != OSC_DENSE) return fail(OSC_EINVAL, "kernel choice applies to dense systems");
             if (value < 0 || value > 3) return fail(OSC_EINVAL, "dense kernel must be 0, 1, 2 or 3");
             if (value == 2 && !(s->prec == OSC_F32 && s->F1))

@@ -45,32 +45,6 @@ __device__ __forceinline__ T fmat(T a, T b, T c) {
     else return __builtin_fma(a, b, c);
 }
 
-// Whole-wave DPP shifts: lane i receives lane i-1 (from_left) or lane i+1
-// (from_right); a lane whose source lies outside the wave (lane 0 shifting
-// right, lane 63 shifting left) receives 0: with BC (bound_ctrl) set the
-// shift itself writes the 0, else the lane keeps the 0 it was given first.
-template <bool BC>
-__device__ __forceinline__ int shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, BC); }
-template <bool BC>
-__device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, BC); }
-
-template <bool BC>
-__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, shr1<BC>(__builtin_bit_cast(int, v))); }
-template <bool BC>
-__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, shl1<BC>(__builtin_bit_cast(int, v))); }
-template <bool BC>
-__device__ __forceinline__ double from_left(double v) {
-    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    unsigned lo = (unsigned)shr1<BC>((int)(unsigned)b), hi = (unsigned)shr1<BC>((int)(unsigned)(b >> 32));
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-template <bool BC>
-__device__ __forceinline__ double from_right(double v) {
-    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    unsigned lo = (unsigned)shl1<BC>((int)(unsigned)b), hi = (unsigned)shl1<BC>((int)(unsigned)(b >> 32));
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
 // FREE: the lane's last DOF is the chain's free end (LPI == 1 and s == DPL),
 // whose right coefficient is exactly zero; its terms are then left out at
 // compile time (same results: a product with +-0 added to a finite value).

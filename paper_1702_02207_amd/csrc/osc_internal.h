@@ -50,6 +50,32 @@ __device__ __forceinline__ void rk4_increments(T w, T P, T Q, T P2, T Q2, T &dx,
     dw = fma_t(T(-0.5), u, -P);
 }
 
+// Whole-wave DPP shifts: lane i receives lane i-1 (from_left) or lane i+1
+// (from_right); a lane whose source lies outside the wave (lane 0 shifting
+// right, lane 63 shifting left) receives 0: with BC (bound_ctrl) set the
+// shift itself writes the 0, else the lane keeps the 0 it was given first.
+template <bool BC>
+__device__ __forceinline__ int shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, BC); }
+template <bool BC>
+__device__ __forceinline__ int shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, BC); }
+
+template <bool BC>
+__device__ __forceinline__ float from_left(float v) { return __builtin_bit_cast(float, shr1<BC>(__builtin_bit_cast(int, v))); }
+template <bool BC>
+__device__ __forceinline__ float from_right(float v) { return __builtin_bit_cast(float, shl1<BC>(__builtin_bit_cast(int, v))); }
+template <bool BC>
+__device__ __forceinline__ double from_left(double v) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    unsigned lo = (unsigned)shr1<BC>((int)(unsigned)b), hi = (unsigned)shr1<BC>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <bool BC>
+__device__ __forceinline__ double from_right(double v) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    unsigned lo = (unsigned)shl1<BC>((int)(unsigned)b), hi = (unsigned)shl1<BC>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // device memory pool with an HBM budget (pool.cpp)
 // ---------------------------------------------------------------------------
@@ -305,6 +331,7 @@ struct DrivenLaunch {
     int32_t s;
     int32_t shared;            // dense: one operator for every instance
     int32_t nbuf;              // LDS stage buffers (set by driven_launch)
+    int32_t force_workgroup;   // chains: 1 = the workgroup kernel even where registers would do (tests)
     ChainCoef<T> c;            // chains
     const T *Bh, *Bl;          // dense: h^2 A column-major, [nsys][s][s]
     const double *h;           // chains [batch], dense [nsys]

@@ -217,3 +217,25 @@ def test_driven_error_returns():
         assert e.value.status == osc.OSC_ENOTSUP
     finally:
         sysm.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("s", [2, 37, 700, 1024])
+def test_driven_chain_register_and_workgroup_kernels_agree(prec, s):
+    """Chains of s <= 1024 run in registers (DPP halo); the one-workgroup
+    kernel (OSC_CFG_DENSE_KERNEL = 1) computes the same scheme: both within
+    the tolerance of the oracle and of each other."""
+    w, alpha, beta, F, W = _chain_case(990 + s, 6, s, 800, 200)
+    out = []
+    for kern in (0, 1):
+        sysm = osc.System("chain", "rk4", prec, w.m, w.k, w.dt).create()
+        try:
+            sysm.set_config(osc.CFG_DENSE_KERNEL, kern)
+            out.append(_run(sysm, w, prec, alpha, beta, F, W))
+        finally:
+            sysm.close()
+    x0, v0 = f32_inputs(w) if prec == "f32" else (w.x0, w.v0)
+    ref = oracle.chain_driven(w.m, w.k, w.dt, alpha, beta, F, W, x0, v0, w.nsteps, w.out_stride)
+    for got in out:
+        ex, ev = _errs(got, ref)
+        assert ex < TOL[prec] and ev < TOL[prec], (s, ex, ev)
