@@ -395,6 +395,27 @@ def serve_pass(args, method="rk4", prec="f32"):
     arr = serve.poisson_arrivals(len(reqs), qps, seed=1702022074)
     run = serve.run_stream(reqs, arr, method=method, prec=prec, hbm_budget=args.hbm_budget)
 
+    # slowdown against the request served alone, on a seeded sample that
+    # always holds the largest request of each kind
+    rng = np.random.default_rng(1702022076)
+    work_of = np.array([r.system.s * r.system.nsteps for r in reqs])
+    largest = [int(np.argmax(np.where([r.kind == k for r in reqs], work_of, -1))) for k in ("chain", "dense")]
+    sample = sorted(set(largest) | set(rng.choice(len(reqs), min(args.slowdown_sample, len(reqs)), replace=False).tolist()))
+    _log(f"[bench] serving: {len(sample)} requests alone (slowdown reference)")
+    alone = serve.alone_latencies(reqs, sample, method=method, prec=prec, hbm_budget=args.hbm_budget)
+
+    def slowdown(res):
+        sl = {"chain": [], "dense": []}
+        for i in sample:
+            if res["results"][i] is not None:
+                sl[reqs[i].kind].append(res["results"][i]["latency_s"] / alone[i])
+        out = {}
+        for kind, v in sl.items():
+            if v:
+                v = np.array(v)
+                out[kind] = {"requests": int(v.size), "median": float(np.median(v)), "max": float(v.max())}
+        return out
+
     def per_kind(res):
         d = {}
         for kind in ("chain", "dense"):
@@ -410,11 +431,12 @@ def serve_pass(args, method="rk4", prec="f32"):
         "p50_latency_s": run["p50_latency_s"], "p99_latency_s": run["p99_latency_s"],
         "mean_latency_s": run["mean_latency_s"], "dof_steps_per_s": run["dof_steps_per_s"],
         "makespan_s": run["makespan_s"], "per_kind": per_kind(run), "failed": run["failed"],
+        "slowdown_vs_alone": slowdown(run), "alone_sample": len(sample),
         "hbm_peak_bytes": run["hbm_peak_bytes"], "iterations": run["iterations"],
         "worker_setup_s": run["worker_setup_s"], "worker_iterate_s": run["worker_iterate_s"],
         "saturation": {"requests_per_s": sat_qps, "dof_steps_per_s": sat["dof_steps_per_s"],
                        "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"],
-                       "per_kind": per_kind(sat)},
+                       "per_kind": per_kind(sat), "slowdown_vs_alone": slowdown(sat)},
     }
 
 
@@ -475,6 +497,8 @@ def main():
     ap.add_argument("--qps", type=float, default=0.0, help="c5: arrival rate (0 = load x saturation)")
     ap.add_argument("--load", type=float, default=0.5, help="c5: fraction of the saturation rate")
     ap.add_argument("--hbm-budget", type=int, default=32 << 30, help="c5: server HBM budget in bytes")
+    ap.add_argument("--slowdown-sample", type=int, default=16,
+                    help="served stream: requests also run alone for their slowdown (plus the largest of each kind)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain elementwise copy of 1 GiB (reads 1 GiB, writes 1 GiB) "
                          "to calibrate the FETCH_SIZE / WRITE_SIZE counters")

@@ -12,9 +12,14 @@
 //      (captured step graphs) on a stream of their own;
 //   3. retires finished requests: results are copied to host memory, device
 //      memory and the slot are released, and waiters are woken.
-// A request's chunk length is a function of the request alone, and every
-// kernel computes an instance independently of its neighbours in a launch,
-// so results do not depend on what else is in flight.
+// Every kernel computes an instance independently of its neighbours in a
+// launch, and a run split into chunks gives bitwise the result of one launch
+// (the compensated state and every schedule of the integrators are tied to
+// global step indices), so results do not depend on what else is in flight
+// nor on where the chunks end.  Chunk lengths aim at a fixed GPU time per
+// iteration; seconds per step come from a per-shape estimate that each
+// iteration updates from events around its launches (a fixed formula until a
+// shape has been seen).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -94,13 +99,35 @@ int64_t estimate_bytes(const osc_desc &d, int64_t nframes) {
     return (int64_t)b;
 }
 
-// Estimated seconds per step of one instance, used only to size chunks.
-double step_seconds(const Req &r) {
+// First guess of the seconds per step of one instance, before its shape's
+// launches have been timed; used only to size chunks.
+double step_seconds_guess(const Req &r) {
     const double s = r.desc.s;
     if (r.desc.kind == OSC_CHAIN) return 2e-7 + 4e-9 * s;
     if (r.split) return 2.0e-5 + 8e-12 * s * s;
     if (r.mfma) return 1e-6 + 2e-11 * s * s;
     return 2e-6 + 1.2e-9 * s * s;
+}
+
+// The launch shape a request's chunks run in: path, method, precision and
+// the size class that selects the kernel.
+uint64_t shape_key(const Req &r) {
+    uint64_t path, cls;
+    const osc_sys *sy = r.sys;
+    if (r.desc.kind == OSC_CHAIN) {
+        path = 0;
+        cls = sy ? (((uint64_t)sy->cfg.lpi << 16) | (uint64_t)sy->cfg.dpl) : (uint64_t)r.desc.s;
+    } else if (r.split) {
+        path = 3;
+        cls = (uint64_t)((r.desc.s + 63) / 64);
+    } else if (r.mfma) {
+        path = 1;
+        cls = (uint64_t)dense_mfma_pad(r.desc.s);
+    } else {
+        path = 2;
+        cls = (uint64_t)dense_vec_bucket(r.desc.s);
+    }
+    return (path << 56) | ((uint64_t)r.desc.method << 48) | ((uint64_t)r.desc.prec << 40) | cls;
 }
 
 struct Server {
@@ -131,9 +158,31 @@ struct Server {
     // to one host image at its own 256-byte aligned offset, the image goes to
     // the device in one copy, and each launch reads its list at that offset
     // once the copy has completed.
+    // seconds per step of each launch shape (exponential average of timed launches)
+    std::map<uint64_t, double> step_est;
+    std::vector<hipEvent_t> event_pool;   // reused timing events
+    size_t events_used = 0;
+    struct Timed {
+        hipEvent_t a, b;
+        uint64_t key;
+        int64_t steps;   // the longest chunk in the launch
+    };
+    std::vector<Timed> timed;
+    hipEvent_t event();                   // next event of the pool (nullptr if none could be made)
+    double step_seconds(const Req &r) const {
+        auto it = step_est.find(shape_key(r));
+        return it != step_est.end() ? it->second : step_seconds_guess(r);
+    }
+    int64_t chunk_of(const Req &r) const {
+        int64_t c = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(r)));
+        if (r.split) c = std::max<int64_t>(64, c / 64 * 64);   // whole captured graphs
+        return c;
+    }
+
     struct WorkLists {
         std::vector<unsigned char> image;
         std::vector<std::function<void(const char *dev, hipStream_t st)>> launches;
+        std::vector<std::pair<uint64_t, int64_t>> shapes;   // per launch: shape key, longest chunk
         size_t append(const void *src, size_t bytes) {
             const size_t off = image.size();
             image.resize(off + (bytes + 255) / 256 * 256);
@@ -174,6 +223,15 @@ void Server::finish(Req *r, osc_status st, const std::string &msg) {
     cv_done.notify_all();
 }
 
+hipEvent_t Server::event() {
+    if (events_used < event_pool.size()) return event_pool[events_used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    event_pool.push_back(e);
+    ++events_used;
+    return e;
+}
+
 bool Server::setup(Req *r) {
     const size_t s = (size_t)r->desc.s;
     r->hxe.assign(s * r->elem, 0);
@@ -181,7 +239,7 @@ bool Server::setup(Req *r) {
     r->hxf.assign(r->nframes * s * r->elem, 0);
     r->hvf.assign(r->nframes * s * r->elem, 0);
     if (cfg.fake_executor) {
-        r->chunk = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(*r)));
+        r->chunk = chunk_of(*r);
         return true;
     }
     osc_desc d = r->desc;
@@ -216,8 +274,7 @@ bool Server::setup(Req *r) {
         finish(r, OSC_EDEVICE, "upload of the initial state failed");
         return false;
     }
-    r->chunk = std::max<int64_t>(16, (int64_t)(cfg.chunk_us * 1e-6 / step_seconds(*r)));
-    if (r->split) r->chunk = std::max<int64_t>(64, r->chunk / 64 * 64);   // whole captured graphs
+    r->chunk = chunk_of(*r);
     // the setup stream is drained; from here on the handle's own stream is
     // one the worker drains every iteration, so the completion path never
     // waits behind another request's setup
@@ -233,6 +290,12 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
     std::map<std::pair<int, int>, std::vector<DenseItem<T>>> denses;       // (method, smax bucket)
     std::map<std::pair<int, int>, int> dense_smax;
     std::map<std::pair<int, int>, std::vector<DenseMfmaItem>> mfmas;       // (method, padded s)
+    std::map<std::pair<int, int64_t>, std::pair<uint64_t, int64_t>> chain_shape;   // shape key, longest chunk
+    std::map<std::pair<int, int>, std::pair<uint64_t, int64_t>> dense_shape, mfma_shape;
+    auto note = [](std::pair<uint64_t, int64_t> &sh, const Req *r, int64_t c) {
+        sh.first = shape_key(*r);
+        sh.second = std::max(sh.second, c);
+    };
     const size_t want_elem = sizeof(T);
     for (size_t i = 0; i < act.size(); ++i) {
         Req *r = act[i];
@@ -262,6 +325,7 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
             it.b = 0;
             const int64_t key = ((int64_t)sy->cfg.lpi << 16) | sy->cfg.dpl;
             chains[{(int)sy->method, key}].push_back(it);
+            note(chain_shape[{(int)sy->method, key}], r, c);
         } else if (std::is_same<T, float>::value && sy->F1) {
             // matrix cores, one workgroup per request (operator resident in registers)
             DenseMfmaItem it{};
@@ -288,6 +352,7 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
             a.load_mode = load;
             a.store_mode = store;
             mfmas[{(int)sy->method, dense_mfma_pad(sy->s)}].push_back(it);
+            note(mfma_shape[{(int)sy->method, dense_mfma_pad(sy->s)}], r, c);
         } else if (!r->split) {
             DenseItem<T> it{};
             it.L.batch = 1;
@@ -313,6 +378,7 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
             const std::pair<int, int> key{(int)sy->method, dense_vec_bucket(sy->s)};
             denses[key].push_back(it);
             dense_smax[key] = std::max(dense_smax[key], (int)sy->s);
+            note(dense_shape[key], r, c);
         } else {
             DenseSplitLaunch<T> a{};
             split_launch_base(sy, a);
@@ -328,8 +394,11 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
             a.load_mode = load;
             a.store_mode = store;
             // the step graph's arguments do not change between chunks of a request
-            osc_status st = dense_split_run<T>(a, sy->method, streams[next_stream], &sy->split_graph,
-                                               &sy->split_graph_len, 64);
+            hipStream_t sst = streams[next_stream];
+            hipEvent_t e0 = event(), e1 = event();
+            if (e0) (void)hipEventRecord(e0, sst);
+            osc_status st = dense_split_run<T>(a, sy->method, sst, &sy->split_graph, &sy->split_graph_len, 64);
+            if (e0 && e1 && hipEventRecord(e1, sst) == hipSuccess) timed.push_back({e0, e1, shape_key(*r), c});
             next_stream = (next_stream + 1) % kStreams;
             if (st != OSC_OK) r->status = st;
         }
@@ -342,6 +411,7 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
         wl.launches.push_back([=](const char *dev, hipStream_t st) {
             (void)chain_launch_items<T>(reinterpret_cast<const ChainItem<T> *>(dev + off), n, method, cfgc, st);
         });
+        wl.shapes.push_back(chain_shape[g.first]);
     }
     for (auto &g : denses) {
         const size_t off = wl.append(g.second.data(), g.second.size() * sizeof(DenseItem<T>));
@@ -350,6 +420,7 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
         wl.launches.push_back([=](const char *dev, hipStream_t st) {
             (void)dense_launch_items<T>(reinterpret_cast<const DenseItem<T> *>(dev + off), n, smax, method, st);
         });
+        wl.shapes.push_back(dense_shape[g.first]);
     }
     for (auto &g : mfmas) {
         const size_t off = wl.append(g.second.data(), g.second.size() * sizeof(DenseMfmaItem));
@@ -358,6 +429,7 @@ void Server::collect_groups(std::vector<Req *> &act, std::vector<int64_t> &cnt, 
         wl.launches.push_back([=](const char *dev, hipStream_t st) {
             (void)dense_mfma_launch_items(reinterpret_cast<const DenseMfmaItem *>(dev + off), n, pad, method, st);
         });
+        wl.shapes.push_back(mfma_shape[g.first]);
     }
 }
 
@@ -398,11 +470,15 @@ void Server::launch_lists(WorkLists &wl, std::vector<Req *> &act, int &next_stre
         for (Req *r : act) r->status = OSC_EDEVICE;
         return;
     }
-    for (auto &launch : wl.launches) {
+    for (size_t i = 0; i < wl.launches.size(); ++i) {
         hipStream_t st = streams[next_stream];
         next_stream = (next_stream + 1) % kStreams;
         (void)hipStreamWaitEvent(st, ready, 0);
-        launch(static_cast<const char *>(items), st);
+        hipEvent_t e0 = event(), e1 = event();
+        if (e0) (void)hipEventRecord(e0, st);
+        wl.launches[i](static_cast<const char *>(items), st);
+        if (e0 && e1 && hipEventRecord(e1, st) == hipSuccess)
+            timed.push_back({e0, e1, wl.shapes[i].first, wl.shapes[i].second});
     }
     (void)hipEventDestroy(ready);
 }
@@ -410,9 +486,12 @@ void Server::launch_lists(WorkLists &wl, std::vector<Req *> &act, int &next_stre
 void Server::run_iteration(std::vector<Req *> &act) {
     std::vector<int64_t> cnt(act.size());
     double sim = 0.0;
+    timed.clear();
+    events_used = 0;
     for (size_t i = 0; i < act.size(); ++i) {
+        act[i]->chunk = chunk_of(*act[i]);
         cnt[i] = std::min(act[i]->chunk, act[i]->nsteps - act[i]->done);
-        sim = std::max(sim, cnt[i] * step_seconds(*act[i]));
+        sim = std::max(sim, cnt[i] * step_seconds_guess(*act[i]));
     }
     if (cfg.fake_executor) {
         std::this_thread::sleep_for(std::chrono::duration<double>(std::min(sim, 0.002)));
@@ -423,6 +502,15 @@ void Server::run_iteration(std::vector<Req *> &act) {
         collect_groups<double>(act, cnt, wl, next_stream);
         launch_lists(wl, act, next_stream);
         for (auto &st : streams) (void)hipStreamSynchronize(st);
+        // seconds per step of each shape from this iteration's launches
+        for (const Timed &t : timed) {
+            float ms = 0.0f;
+            if (t.steps <= 0 || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess || !(ms > 0.0f)) continue;
+            const double per_step = 1e-3 * (double)ms / (double)t.steps;
+            auto it = step_est.find(t.key);
+            if (it == step_est.end()) step_est[t.key] = per_step;
+            else it->second = 0.5 * it->second + 0.5 * per_step;
+        }
     }
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -688,6 +776,7 @@ void osc_server_destroy(osc_server *srv) {
     if (S.setup_worker.joinable()) S.setup_worker.join();
     for (auto &kv : S.all) delete kv.second;
     S.all.clear();
+    for (hipEvent_t e : S.event_pool) (void)hipEventDestroy(e);
     if (S.stage) (void)hipHostFree(S.stage);
     pool_free(S.items);
     for (auto &st : S.streams)

@@ -24,6 +24,18 @@ def submit_request(srv: "osc.Server", req, method: str = "rk4", prec: str = "f32
     return srv.submit("dense", method, prec, w.M, w.K, w.dt, w.x0[0], w.v0[0], w.nsteps, w.out_stride)
 
 
+def alone_latencies(reqs, idx, method: str = "rk4", prec: str = "f32", hbm_budget: int = 0,
+                    timeout: float = 600.0) -> dict:
+    """Latency of each request idx[j] served alone (one request in the server
+    at a time), the reference for its slowdown in a stream."""
+    out = {}
+    with osc.Server(hbm_budget=hbm_budget) as srv:
+        for i in idx:
+            t = submit_request(srv, reqs[i], method, prec)
+            out[int(i)] = srv.wait(t, timeout=timeout)["latency_s"]
+    return out
+
+
 def poisson_arrivals(n: int, qps: float, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.cumsum(rng.exponential(1.0 / qps, n))
