@@ -53,8 +53,11 @@ struct Phase {
     __device__ void set(int64_t n) {
         sincos(wh * (double)n, &s, &c);
     }
+    // The rounding is spelled out (one product, then one fused
+    // multiply-add) so that every inlined copy, in and out of the step loop,
+    // computes bit for bit the same rotation.
     __device__ void half() {
-        const double nc = c * rc - s * rs, ns = s * rc + c * rs;
+        const double nc = __builtin_fma(c, rc, -(s * rs)), ns = __builtin_fma(s, rc, c * rs);
         c = nc;
         s = ns;
     }
@@ -275,7 +278,9 @@ __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
 // At least two waves per SIMD except for FP64 with 16 DOFs per lane: the
 // FP32 16-DOF kernel then spills ~20 registers to scratch and still runs
 // 1.8x faster than at one wave per SIMD; the FP64 one would spill ~370.
-template <typename T, int DPL, int LPI>
+// EX: bit 0 Rayleigh beta != 0 (the stiffness-proportional damping term),
+// bit 1 a force; fixed per launch, so that each step is one basic block.
+template <typename T, int DPL, int LPI, int EX>
 __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 2)
     driven_chain_kernel(DrivenLaunch<T> a) {
     constexpr bool COMP = std::is_same<T, float>::value;
@@ -288,8 +293,7 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     const size_t base = (size_t)(active ? b : 0) * s, plane = (size_t)a.batch * s;
     const double h = active ? a.h[b] : 1.0;
     const T dampw = (T)(a.alpha * h), dampb = (T)(a.beta / h);
-    const bool use_beta = a.beta != 0.0;
-    const bool forced = a.f != nullptr;
+    constexpr bool use_beta = (EX & 1) != 0, forced = (EX & 2) != 0;
 
     T clh[DPL], crh[DPL], cll[DPL], crl[DPL], fh[DPL], x[DPL], xl[DPL], w[DPL], wl[DPL];
 #pragma unroll
@@ -337,12 +341,14 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
             next = from_right<true>(u[0]);
         }
     };
-    // kw = -B X (split) - a W - b B W + f c
-    auto slope = [&](const T (&X)[DPL], const T (&W)[DPL], T force, T (&kw)[DPL]) {
+    // kw = -B X (split) - a W - b B W + f c; BETA and FORCED are fixed for
+    // the whole launch and compiled in, so that the step is one basic block
+    auto slope = [&](auto beta_c, auto forced_c, const T (&X)[DPL], const T (&W)[DPL], T force, T (&kw)[DPL]) {
+        constexpr bool BETA = decltype(beta_c)::value, FORCED = decltype(forced_c)::value;
         T xp, xn;
         halo(X, xp, xn);
         T wp = T(0), wn = T(0);
-        if (use_beta) halo(W, wp, wn);
+        if constexpr (BETA) halo(W, wp, wn);
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
             const T xm = j > 0 ? X[j > 0 ? j - 1 : 0] : xp, xr = j + 1 < DPL ? X[j + 1 < DPL ? j + 1 : j] : xn;
@@ -350,13 +356,13 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
             T p = fma_t(clh[j], el, -crh[j] * er);
             if constexpr (COMP) p += fma_t(cll[j], el, -crl[j] * er);
             T acc = -p;
-            if (use_beta) {
+            if constexpr (BETA) {
                 const T wm = j > 0 ? W[j > 0 ? j - 1 : 0] : wp, wr = j + 1 < DPL ? W[j + 1 < DPL ? j + 1 : j] : wn;
                 const T q = fma_t(clh[j], W[j] - wm, -crh[j] * (wr - W[j]));
                 acc = fma_t(-dampb, q, acc);
             }
             acc = fma_t(-dampw, W[j], acc);
-            if (forced) acc = fma_t(fh[j], force, acc);
+            if constexpr (FORCED) acc = fma_t(fh[j], force, acc);
             kw[j] = acc;
         }
     };
@@ -389,49 +395,96 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     int64_t n = a.n0;
     const int64_t nend = a.n0 + a.nsteps;
     if (stride > 0 && untouched && n % stride == 0) write_frame(n / stride, true);
-    while (n < nend) {
-        if (forced && n % kAnchor == 0) ph.set(n);
-        const T f0 = (T)ph.c;
-        if (forced) ph.half();
-        const T fhalf = (T)ph.c;
-        if (forced) ph.half();
-        const T f1 = (T)ph.c;
-        T X[DPL], W[DPL], k[DPL], sx[DPL], sw[DPL];
-        slope(x, w, f0, k);
+    auto steps = [&](auto beta_c, auto forced_c) {
+        constexpr bool FORCED = decltype(forced_c)::value;
+        while (n < nend) {
+            if (FORCED && n % kAnchor == 0) ph.set(n);
+            const T f0 = (T)ph.c;
+            if (FORCED) ph.half();
+            const T fhalf = (T)ph.c;
+            if (FORCED) ph.half();
+            const T f1 = (T)ph.c;
+            if constexpr (COMP) {
+                // The stages read only the high parts, so the low parts collect
+                // the step's slope terms as they are formed (smallest first):
+                //   dx = w + (k1 + k2 + k3) / 6,  dw = (k1 + 2 k2 + 2 k3 + k4) / 6
+                // and one Kahan step per variable adds them at the end; no
+                // per-DOF partial sums stay live across the stages.
+                T X[DPL], W[DPL], k[DPL];
+                slope(beta_c, forced_c, x, w, f0, k);
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            sx[j] = k[j];
-            sw[j] = k[j];
-            X[j] = fma_t(T(0.5), w[j], x[j]);
-            W[j] = fma_t(T(0.5), k[j], w[j]);
-        }
-        slope(X, W, fhalf, k);
+                for (int j = 0; j < DPL; ++j) {
+                    X[j] = fma_t(T(0.5), w[j], x[j]);
+                    W[j] = fma_t(T(0.5), k[j], w[j]);
+                    xl[j] = fma_t(T(1.0 / 6.0), k[j], xl[j]);
+                    wl[j] = fma_t(T(1.0 / 6.0), k[j], wl[j]);
+                }
+                slope(beta_c, forced_c, X, W, fhalf, k);
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            sx[j] += k[j];
-            sw[j] = fma_t(T(2), k[j], sw[j]);
-            X[j] = fma_t(T(0.5), W[j], x[j]);
-            W[j] = fma_t(T(0.5), k[j], w[j]);
-        }
-        slope(X, W, fhalf, k);
+                for (int j = 0; j < DPL; ++j) {
+                    X[j] = fma_t(T(0.5), W[j], x[j]);
+                    W[j] = fma_t(T(0.5), k[j], w[j]);
+                    xl[j] = fma_t(T(1.0 / 6.0), k[j], xl[j]);
+                    wl[j] = fma_t(T(1.0 / 3.0), k[j], wl[j]);
+                }
+                slope(beta_c, forced_c, X, W, fhalf, k);
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            sx[j] += k[j];
-            sw[j] = fma_t(T(2), k[j], sw[j]);
-            X[j] = x[j] + W[j];
-            W[j] = w[j] + k[j];
-        }
-        slope(X, W, f1, k);
+                for (int j = 0; j < DPL; ++j) {
+                    X[j] = x[j] + W[j];
+                    W[j] = w[j] + k[j];
+                    xl[j] = fma_t(T(1.0 / 6.0), k[j], xl[j]);
+                    wl[j] = fma_t(T(1.0 / 3.0), k[j], wl[j]);
+                }
+                slope(beta_c, forced_c, X, W, f1, k);
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            const T dx = fma_t(T(1.0 / 6.0), sx[j], w[j]);
-            const T dw = (sw[j] + k[j]) * T(1.0 / 6.0);
-            comp_add(x[j], xl[j], dx);
-            comp_add(w[j], wl[j], dw);
+                for (int j = 0; j < DPL; ++j) {
+                    wl[j] = fma_t(T(1.0 / 6.0), k[j], wl[j]);
+                    const T y = w[j] + xl[j];
+                    T t = x[j] + y;
+                    xl[j] = y - (t - x[j]);
+                    x[j] = t;
+                    t = w[j] + wl[j];
+                    wl[j] = wl[j] - (t - w[j]);
+                    w[j] = t;
+                }
+            } else {
+                T X[DPL], W[DPL], k[DPL], sx[DPL], sw[DPL];
+                slope(beta_c, forced_c, x, w, f0, k);
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    sx[j] = k[j];
+                    sw[j] = k[j];
+                    X[j] = fma_t(T(0.5), w[j], x[j]);
+                    W[j] = fma_t(T(0.5), k[j], w[j]);
+                }
+                slope(beta_c, forced_c, X, W, fhalf, k);
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    sx[j] += k[j];
+                    sw[j] = fma_t(T(2), k[j], sw[j]);
+                    X[j] = fma_t(T(0.5), W[j], x[j]);
+                    W[j] = fma_t(T(0.5), k[j], w[j]);
+                }
+                slope(beta_c, forced_c, X, W, fhalf, k);
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    sx[j] += k[j];
+                    sw[j] = fma_t(T(2), k[j], sw[j]);
+                    X[j] = x[j] + W[j];
+                    W[j] = w[j] + k[j];
+                }
+                slope(beta_c, forced_c, X, W, f1, k);
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    x[j] += fma_t(T(1.0 / 6.0), sx[j], w[j]);
+                    w[j] += (sw[j] + k[j]) * T(1.0 / 6.0);
+                }
+            }
+            ++n;
+            if (stride > 0 && n % stride == 0) write_frame(n / stride, false);
         }
-        ++n;
-        if (stride > 0 && n % stride == 0) write_frame(n / stride, false);
-    }
+    };
+    steps(std::integral_constant<bool, use_beta>{}, std::integral_constant<bool, forced>{});
 
     bool ok = true;
     const bool copy_input = untouched && a.nsteps == 0;
@@ -458,7 +511,11 @@ template <typename T, int DPL, int LPI>
 osc_status launch_chain_regs(const DrivenLaunch<T> &a, hipStream_t st) {
     const int64_t threads = a.batch * LPI;
     const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((driven_chain_kernel<T, DPL, LPI>), dim3(blocks), dim3(kThreads), 0, st, a);
+    const int ex = (a.beta != 0.0 ? 1 : 0) | (a.f ? 2 : 0);
+    if (ex == 0) hipLaunchKernelGGL((driven_chain_kernel<T, DPL, LPI, 0>), dim3(blocks), dim3(kThreads), 0, st, a);
+    else if (ex == 1) hipLaunchKernelGGL((driven_chain_kernel<T, DPL, LPI, 1>), dim3(blocks), dim3(kThreads), 0, st, a);
+    else if (ex == 2) hipLaunchKernelGGL((driven_chain_kernel<T, DPL, LPI, 2>), dim3(blocks), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL((driven_chain_kernel<T, DPL, LPI, 3>), dim3(blocks), dim3(kThreads), 0, st, a);
     OSC_HIP(hipGetLastError());
     return OSC_OK;
 }
