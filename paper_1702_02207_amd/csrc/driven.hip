@@ -272,12 +272,26 @@ __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
 // per instance (LPI = 64, DPL consecutive DOFs per lane, s <= 64 DPL).  The
 // stencil's neighbouring values across lanes come from whole-wave DPP shifts
 // (zero outside the wave: the wall, and beyond the free end, whose
-// coefficient is zero); no LDS, no barrier.  Same stage form and force phase
-// as the workgroup kernel; the state is updated by a Kahan sum every step, so
-// its high part is the rounded state itself.
-// At least two waves per SIMD except for FP64 with 16 DOFs per lane: the
-// FP32 16-DOF kernel then spills ~20 registers to scratch and still runs
-// 1.8x faster than at one wave per SIMD; the FP64 one would spill ~370.
+// coefficient is zero); no LDS, no barrier.
+//
+// The step is the same RK4 map as the stage form above, in the form a linear
+// system with constant coefficients allows.  With y = (x, w), the operator
+// L y = (w, -B x - a w - b B w) (a = alpha h, b = beta / h) and the force
+// direction e = (0, h^2 f), the four stages with force phases c0, ch, ch, c1
+// (at t_n, t_n + h/2, t_n + h) sum to
+//     y_{n+1} = y + z1 + z2/2 + z3/6 + z4/24,   z1 = L y + g1 e,
+//     z_k = L z_{k-1} + g_k e,  g1 = c0, g2 = 2 (ch - c0), g3 = 0,
+//     g4 = 4 (c0 - 2 ch + c1)
+// (expand k1..k4 and match the coefficients of L^j e).  The x-part of z_k is
+// the w-part of z_{k-1}, so B of it is already known: one step takes B x
+// (split coefficients: it is the dominant term), B w, B z1_w, B z2_w and,
+// with stiffness damping, B z3_w -- five stencils against the stage form's
+// eight, four of them with the high coefficients only.  The g_k are formed
+// in FP64 from the FP64 phase before rounding to T.  The low parts of x and
+// w collect the z terms as they are formed and one Kahan step per variable
+// ends the step (FP64: a plain update), so chunked, static and real-time
+// runs agree bitwise as for the stage form.  Two waves per SIMD except for
+// FP64 with 16 DOFs per lane (one).
 // EX: bit 0 Rayleigh beta != 0 (the stiffness-proportional damping term),
 // bit 1 a force; fixed per launch, so that each step is one basic block.
 template <typename T, int DPL, int LPI, int EX>
@@ -341,29 +355,20 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
             next = from_right<true>(u[0]);
         }
     };
-    // kw = -B X (split) - a W - b B W + f c; BETA and FORCED are fixed for
-    // the whole launch and compiled in, so that the step is one basic block
-    auto slope = [&](auto beta_c, auto forced_c, const T (&X)[DPL], const T (&W)[DPL], T force, T (&kw)[DPL]) {
-        constexpr bool BETA = decltype(beta_c)::value, FORCED = decltype(forced_c)::value;
-        T xp, xn;
-        halo(X, xp, xn);
-        T wp = T(0), wn = T(0);
-        if constexpr (BETA) halo(W, wp, wn);
+    // out = B U (high coefficients; SPLIT: plus the low coefficients' part)
+    auto bop = [&](auto split_c, const T (&U)[DPL], T (&out)[DPL]) {
+        constexpr bool SPLIT = decltype(split_c)::value && COMP;
+        T up, un;
+        halo(U, up, un);
+        T el = U[0] - up;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const T xm = j > 0 ? X[j > 0 ? j - 1 : 0] : xp, xr = j + 1 < DPL ? X[j + 1 < DPL ? j + 1 : j] : xn;
-            const T el = X[j] - xm, er = xr - X[j];
+            const T ur = j + 1 < DPL ? U[j + 1 < DPL ? j + 1 : j] : un;
+            const T er = ur - U[j];
             T p = fma_t(clh[j], el, -crh[j] * er);
-            if constexpr (COMP) p += fma_t(cll[j], el, -crl[j] * er);
-            T acc = -p;
-            if constexpr (BETA) {
-                const T wm = j > 0 ? W[j > 0 ? j - 1 : 0] : wp, wr = j + 1 < DPL ? W[j + 1 < DPL ? j + 1 : j] : wn;
-                const T q = fma_t(clh[j], W[j] - wm, -crh[j] * (wr - W[j]));
-                acc = fma_t(-dampb, q, acc);
-            }
-            acc = fma_t(-dampw, W[j], acc);
-            if constexpr (FORCED) acc = fma_t(fh[j], force, acc);
-            kw[j] = acc;
+            if constexpr (SPLIT) p += fma_t(cll[j], el, -crl[j] * er);
+            out[j] = p;
+            el = er;
         }
     };
 
@@ -396,88 +401,78 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     const int64_t nend = a.n0 + a.nsteps;
     if (stride > 0 && untouched && n % stride == 0) write_frame(n / stride, true);
     auto steps = [&](auto beta_c, auto forced_c) {
-        constexpr bool FORCED = decltype(forced_c)::value;
+        constexpr bool BETA = decltype(beta_c)::value, FORCED = decltype(forced_c)::value;
+        const std::true_type split{};
+        const std::false_type hi_only{};
         while (n < nend) {
-            if (FORCED && n % kAnchor == 0) ph.set(n);
-            const T f0 = (T)ph.c;
-            if (FORCED) ph.half();
-            const T fhalf = (T)ph.c;
-            if (FORCED) ph.half();
-            const T f1 = (T)ph.c;
-            if constexpr (COMP) {
-                // The stages read only the high parts, so the low parts collect
-                // the step's slope terms as they are formed (smallest first):
-                //   dx = w + (k1 + k2 + k3) / 6,  dw = (k1 + 2 k2 + 2 k3 + k4) / 6
-                // and one Kahan step per variable adds them at the end; no
-                // per-DOF partial sums stay live across the stages.
-                T X[DPL], W[DPL], k[DPL];
-                slope(beta_c, forced_c, x, w, f0, k);
+            T g1 = T(0), g2 = T(0), g4 = T(0);
+            if constexpr (FORCED) {
+                if (n % kAnchor == 0) ph.set(n);
+                const double c0 = ph.c;
+                ph.half();
+                const double ch = ph.c;
+                ph.half();
+                const double c1 = ph.c;
+                g1 = (T)c0;
+                g2 = (T)(2.0 * (ch - c0));
+                g4 = (T)(4.0 * ((c0 - ch) + (c1 - ch)));
+            }
+            // z_{k+1,w} = -B z_{k,x} - a z_{k,w} - b B z_{k,w} + g e, with
+            // z_{k,x} = z_{k-1,w}: Bp holds B z_{k,x}, V the new z_w
+            T Bp[DPL], V[DPL], R[DPL];
+            bop(split, x, R);     // B x
+            bop(hi_only, w, Bp);  // B w = B z1_x
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    X[j] = fma_t(T(0.5), w[j], x[j]);
-                    W[j] = fma_t(T(0.5), k[j], w[j]);
-                    xl[j] = fma_t(T(1.0 / 6.0), k[j], xl[j]);
-                    wl[j] = fma_t(T(1.0 / 6.0), k[j], wl[j]);
-                }
-                slope(beta_c, forced_c, X, W, fhalf, k);
+            for (int j = 0; j < DPL; ++j) {
+                T v = fma_t(-dampw, w[j], -R[j]);
+                if constexpr (BETA) v = fma_t(-dampb, Bp[j], v);
+                if constexpr (FORCED) v = fma_t(fh[j], g1, v);
+                V[j] = v;   // z1_w
+                xl[j] = fma_t(T(0.5), v, xl[j]);
+                wl[j] += v;
+            }
+            bop(hi_only, V, R);   // B z1_w = B z2_x
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    X[j] = fma_t(T(0.5), W[j], x[j]);
-                    W[j] = fma_t(T(0.5), k[j], w[j]);
-                    xl[j] = fma_t(T(1.0 / 6.0), k[j], xl[j]);
-                    wl[j] = fma_t(T(1.0 / 3.0), k[j], wl[j]);
-                }
-                slope(beta_c, forced_c, X, W, fhalf, k);
+            for (int j = 0; j < DPL; ++j) {
+                T v = fma_t(-dampw, V[j], -Bp[j]);
+                if constexpr (BETA) v = fma_t(-dampb, R[j], v);
+                if constexpr (FORCED) v = fma_t(fh[j], g2, v);
+                V[j] = v;   // z2_w
+                Bp[j] = R[j];
+                xl[j] = fma_t(T(1.0 / 6.0), v, xl[j]);
+                wl[j] = fma_t(T(0.5), v, wl[j]);
+            }
+            bop(hi_only, V, R);   // B z2_w = B z3_x
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    X[j] = x[j] + W[j];
-                    W[j] = w[j] + k[j];
-                    xl[j] = fma_t(T(1.0 / 6.0), k[j], xl[j]);
-                    wl[j] = fma_t(T(1.0 / 3.0), k[j], wl[j]);
-                }
-                slope(beta_c, forced_c, X, W, f1, k);
+            for (int j = 0; j < DPL; ++j) {
+                T v = fma_t(-dampw, V[j], -Bp[j]);
+                if constexpr (BETA) v = fma_t(-dampb, R[j], v);
+                V[j] = v;   // z3_w
+                Bp[j] = R[j];
+                xl[j] = fma_t(T(1.0 / 24.0), v, xl[j]);
+                wl[j] = fma_t(T(1.0 / 6.0), v, wl[j]);
+            }
+            if constexpr (BETA) bop(hi_only, V, R);   // B z3_w
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    wl[j] = fma_t(T(1.0 / 6.0), k[j], wl[j]);
-                    const T y = w[j] + xl[j];
+            for (int j = 0; j < DPL; ++j) {
+                T v = fma_t(-dampw, V[j], -Bp[j]);
+                if constexpr (BETA) v = fma_t(-dampb, R[j], v);
+                if constexpr (FORCED) v = fma_t(fh[j], g4, v);
+                wl[j] = fma_t(T(1.0 / 24.0), v, wl[j]);   // z4_w
+                // x += w + (low part), w += (low part)
+                const T y = w[j] + xl[j];
+                if constexpr (COMP) {
                     T t = x[j] + y;
                     xl[j] = y - (t - x[j]);
                     x[j] = t;
                     t = w[j] + wl[j];
                     wl[j] = wl[j] - (t - w[j]);
                     w[j] = t;
-                }
-            } else {
-                T X[DPL], W[DPL], k[DPL], sx[DPL], sw[DPL];
-                slope(beta_c, forced_c, x, w, f0, k);
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    sx[j] = k[j];
-                    sw[j] = k[j];
-                    X[j] = fma_t(T(0.5), w[j], x[j]);
-                    W[j] = fma_t(T(0.5), k[j], w[j]);
-                }
-                slope(beta_c, forced_c, X, W, fhalf, k);
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    sx[j] += k[j];
-                    sw[j] = fma_t(T(2), k[j], sw[j]);
-                    X[j] = fma_t(T(0.5), W[j], x[j]);
-                    W[j] = fma_t(T(0.5), k[j], w[j]);
-                }
-                slope(beta_c, forced_c, X, W, fhalf, k);
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    sx[j] += k[j];
-                    sw[j] = fma_t(T(2), k[j], sw[j]);
-                    X[j] = x[j] + W[j];
-                    W[j] = w[j] + k[j];
-                }
-                slope(beta_c, forced_c, X, W, f1, k);
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    x[j] += fma_t(T(1.0 / 6.0), sx[j], w[j]);
-                    w[j] += (sw[j] + k[j]) * T(1.0 / 6.0);
+                } else {
+                    x[j] += y;
+                    w[j] += wl[j];
+                    xl[j] = T(0);
+                    wl[j] = T(0);
                 }
             }
             ++n;
