@@ -75,6 +75,11 @@ IMPL_PROP_STEP_FLOPS = 29
 # (6) and the next stage's arguments (4); four stages less the first one's
 # arguments, plus the weighted combination (9)
 ALG_DRIVEN_CHAIN_FLOPS = 85
+# the register kernel's form of the same map (FMA = 2): B x with split
+# coefficients (8), four high-coefficient stencils (4 each), the four levels
+# of the recursion with their low-part sums (9 + 10 + 8 + 8) and the two
+# Kahan updates (7)
+IMPL_DRIVEN_CHAIN_FLOPS = 66
 
 WORKLOADS = {
     "c1": dict(kind="chain", method="rk4", prec="f64",
@@ -134,13 +139,15 @@ def make_workload(name):
 
 
 # kernel sources that decide the dominant kernel of each workload family
-TRAFFIC_SOURCES = {"chain": ("chain.hip", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h")}
+TRAFFIC_SOURCES = {"chain": ("chain.hip", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h"),
+                   "driven": ("driven.hip", "osc_internal.h")}
 
 
 def src_hash(workload):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1702_02207_amd", "csrc")
-    for f in TRAFFIC_SOURCES["dense" if workload.startswith("c4") else "chain"]:
+    kind = "dense" if workload.startswith("c4") else "driven" if workload == "c3d" else "chain"
+    for f in TRAFFIC_SOURCES[kind]:
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -300,8 +307,11 @@ def bench_batched(args, name, spec):
         fpd = ALG_DRIVEN_CHAIN_FLOPS
         achieved = fpd * dof_steps / kavg / 1e12
         roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK["fp32"], unit="TFLOP/s",
-                        frac=round(achieved / PEAK["fp32"], 4), traffic=None, kernel="driven_kernel",
-                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd)
+                        frac=round(achieved / PEAK["fp32"], 4), traffic=measured_traffic(name),
+                        kernel="driven_chain_kernel",
+                        kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd,
+                        impl_flops_per_dof_step=IMPL_DRIVEN_CHAIN_FLOPS,
+                        impl_frac=round(IMPL_DRIVEN_CHAIN_FLOPS * dof_steps / kavg / 1e12 / PEAK["fp32"], 4))
     elif kind == "chain":
         fpd = (ALG_CHAIN2_FLOPS if w.s == 2 else ALG_CHAIN_FLOPS)[method]
         impl = IMPL_PROP_STEP_FLOPS if mode == 2 else IMPL_CHAIN_FLOPS[(method, prec)]

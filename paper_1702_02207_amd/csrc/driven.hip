@@ -309,28 +309,77 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     const T dampw = (T)(a.alpha * h), dampb = (T)(a.beta / h);
     constexpr bool use_beta = (EX & 1) != 0, forced = (EX & 2) != 0;
 
-    T clh[DPL], crh[DPL], cll[DPL], crl[DPL], fh[DPL], x[DPL], xl[DPL], w[DPL], wl[DPL];
+    // A lane's DPL consecutive elements of a [batch][s] plane move as 16-byte
+    // vectors when the run is whole and aligned, so that a wave's accesses
+    // fill whole cache lines together instead of one element per line per
+    // instruction.
+    const bool run_whole = active && d0 + DPL <= s;
+    auto load = [&](const auto *src, auto (&dst)[DPL]) {
+        using U = std::remove_const_t<std::remove_pointer_t<decltype(src)>>;
+        constexpr int V = 16 / (int)sizeof(U);
+        typedef U vec_t __attribute__((ext_vector_type(V)));
+        if (DPL % V == 0 && run_whole && ((uintptr_t)(src + base + d0) % 16) == 0) {
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-        const bool own = active && d0 + j < s;
-        const size_t i = base + d0 + j;
-        clh[j] = own ? a.c.clh[i] : T(0);
-        crh[j] = own ? a.c.crh[i] : T(0);
-        cll[j] = (own && COMP) ? a.c.cll[i] : T(0);
-        crl[j] = (own && COMP) ? a.c.crl[i] : T(0);
-        fh[j] = (own && forced) ? (T)(h * h * a.f[i]) : T(0);
-        if (a.load_mode == LOAD_USER) {
-            x[j] = own ? a.x0[i] : T(0);
+            for (int q = 0; q < DPL / V; ++q) {
+                const vec_t v = *reinterpret_cast<const vec_t *>(src + base + d0 + q * V);
+#pragma unroll
+                for (int e = 0; e < V; ++e) dst[q * V + e] = v[e];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) dst[j] = (active && d0 + j < s) ? src[base + d0 + j] : U(0);
+        }
+    };
+    // element j of the lane's run is val(j), formed as it is stored
+    auto store = [&](T *dst, auto val) {
+        constexpr int V = 16 / (int)sizeof(T);
+        typedef T vec_t __attribute__((ext_vector_type(V)));
+        if (DPL % V == 0 && run_whole && ((uintptr_t)(dst + base + d0) % 16) == 0) {
+#pragma unroll
+            for (int q = 0; q < DPL / V; ++q) {
+                vec_t v;
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[e] = val(q * V + e);
+                *reinterpret_cast<vec_t *>(dst + base + d0 + q * V) = v;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j)
+                if (active && d0 + j < s) dst[base + d0 + j] = val(j);
+        }
+    };
+
+    T clh[DPL], crh[DPL], cll[DPL], crl[DPL], fh[DPL], x[DPL], xl[DPL], w[DPL], wl[DPL];
+    load(a.c.clh, clh);
+    load(a.c.crh, crh);
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) cll[j] = crl[j] = fh[j] = T(0);
+    if constexpr (COMP) {
+        load(a.c.cll, cll);
+        load(a.c.crl, crl);
+    }
+    if constexpr (forced) {
+        double fd[DPL];
+        load(a.f, fd);
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) fh[j] = (T)(h * h * fd[j]);
+    }
+    if (a.load_mode == LOAD_USER) {
+        T v0[DPL];
+        load(a.x0, x);
+        load(a.v0, v0);
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
             xl[j] = T(0);
-            const double wd = own ? h * (double)a.v0[i] : 0.0;
+            const double wd = h * (double)v0[j];
             w[j] = (T)wd;
             wl[j] = COMP ? (T)(wd - (double)w[j]) : T(0);
-        } else {
-            x[j] = own ? a.state[i] : T(0);
-            xl[j] = own ? a.state[plane + i] : T(0);
-            w[j] = own ? a.state[2 * plane + i] : T(0);
-            wl[j] = own ? a.state[3 * plane + i] : T(0);
         }
+    } else {
+        load(a.state, x);
+        load(a.state + plane, xl);
+        load(a.state + 2 * plane, w);
+        load(a.state + 3 * plane, wl);
     }
     if constexpr (COMP) {
         // start from a normalised pair (the high part the rounded state)
@@ -365,9 +414,9 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
         for (int j = 0; j < DPL; ++j) {
             const T ur = j + 1 < DPL ? U[j + 1 < DPL ? j + 1 : j] : un;
             const T er = ur - U[j];
-            T p = fma_t(clh[j], el, -crh[j] * er);
-            if constexpr (SPLIT) p += fma_t(cll[j], el, -crl[j] * er);
-            out[j] = p;
+            // the low coefficients' terms first, the dominant product last
+            if constexpr (SPLIT) out[j] = fma_t(clh[j], el, fma_t(-crh[j], er, fma_t(cll[j], el, -crl[j] * er)));
+            else out[j] = fma_t(clh[j], el, -crh[j] * er);
             el = er;
         }
     };
@@ -384,14 +433,23 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
             ph.half();
         }
     }
+    auto xval = [&](int j) { return (T)((double)x[j] + (double)xl[j]); };
+    auto vval = [&](int j) { return (T)(((double)w[j] + (double)wl[j]) / h); };
+    // the caller's x0 / v0 unchanged (frame 0, nsteps = 0)
+    auto copy_out = [&](T *dst, const T *src) {
+        T o[DPL];
+        load(src, o);
+        store(dst, [&](int j) { return o[j]; });
+    };
     auto write_frame = [&](int64_t f, bool initial) {
         const size_t fo = (size_t)f * plane;
-#pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            if (!(active && d0 + j < s)) continue;
-            const size_t i = base + d0 + j;
-            if (a.xf) a.xf[fo + i] = initial ? a.x0[i] : (T)((double)x[j] + (double)xl[j]);
-            if (a.vf) a.vf[fo + i] = initial ? a.v0[i] : (T)(((double)w[j] + (double)wl[j]) / h);
+        if (a.xf) {
+            if (initial) copy_out(a.xf + fo, a.x0);
+            else store(a.xf + fo, xval);
+        }
+        if (a.vf) {
+            if (initial) copy_out(a.vf + fo, a.v0);
+            else store(a.vf + fo, vval);
         }
     };
 
@@ -484,19 +542,22 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     bool ok = true;
     const bool copy_input = untouched && a.nsteps == 0;
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) {
-        if (!(active && d0 + j < s)) continue;
-        const size_t i = base + d0 + j;
-        ok = ok && __builtin_isfinite(x[j]) && __builtin_isfinite(w[j]);
-        if (a.store_mode & STORE_STATE) {
-            a.state[i] = x[j];
-            a.state[plane + i] = xl[j];
-            a.state[2 * plane + i] = w[j];
-            a.state[3 * plane + i] = wl[j];
+    for (int j = 0; j < DPL; ++j)
+        if (active && d0 + j < s) ok = ok && __builtin_isfinite(x[j]) && __builtin_isfinite(w[j]);
+    if (a.store_mode & STORE_STATE) {
+        store(a.state, [&](int j) { return x[j]; });
+        store(a.state + plane, [&](int j) { return xl[j]; });
+        store(a.state + 2 * plane, [&](int j) { return w[j]; });
+        store(a.state + 3 * plane, [&](int j) { return wl[j]; });
+    }
+    if (a.store_mode & STORE_USER) {
+        if (a.xe) {
+            if (copy_input) copy_out(a.xe, a.x0);
+            else store(a.xe, xval);
         }
-        if (a.store_mode & STORE_USER) {
-            if (a.xe) a.xe[i] = copy_input ? a.x0[i] : (T)((double)x[j] + (double)xl[j]);
-            if (a.ve) a.ve[i] = copy_input ? a.v0[i] : (T)(((double)w[j] + (double)wl[j]) / h);
+        if (a.ve) {
+            if (copy_input) copy_out(a.ve, a.v0);
+            else store(a.ve, vval);
         }
     }
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
