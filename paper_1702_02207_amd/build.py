@@ -1,7 +1,8 @@
 """Build libosc.so (HIP, gfx950) in-tree.
 
 Every source under csrc/ is compiled with hipcc for gfx950 only and linked into
-paper_1702_02207_amd/libosc.so.  Packed FP32 instructions are disabled for all
+paper_1702_02207_amd/libosc.so.  The stand-alone measurement programs under
+probe/ (not part of the library) are built next to their sources.  Packed FP32 instructions are disabled for all
 device code (-Xclang -target-feature -Xclang -packed-fp32-ops); the host pass
 warns that it does not know the feature, which is harmless.
 """
@@ -18,6 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosc.so")
+PROBE = os.path.join(HERE, "probe")
 ARCH = os.environ.get("OSC_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -57,6 +59,15 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    for src in sorted(glob.glob(os.path.join(PROBE, "*.hip"))):
+        exe = src[:-len(".hip")]
+        cmd = ["hipcc", *COMMON, src, "-o", exe + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}{r.stderr}")
+        os.replace(exe + ".tmp", exe)
     return LIB
 
 
