@@ -139,7 +139,7 @@ def make_workload(name):
 
 
 # kernel sources that decide the dominant kernel of each workload family
-TRAFFIC_SOURCES = {"chain": ("chain.hip", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h"),
+TRAFFIC_SOURCES = {"chain": ("chain.hip", "chain_run.h", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h"),
                    "driven": ("driven.hip", "osc_internal.h")}
 
 
@@ -452,8 +452,9 @@ def serve_pass(args, method="rk4", prec="f32"):
 
 def realtime_pass(args):
     """The paper's two-mass system (eq. (3), FP64, RK4, dt = 1e-5) stepped in
-    real time: one step per wall-clock period (osc_rt_run), the latency from
-    each release to the result being ready on the host."""
+    real time: one step per wall-clock period, launched per tick (osc_rt_run)
+    or by a resident kernel (osc_rt_run_resident); the latency from each
+    release to the result being ready, as seen by the host."""
     import torch
     from paper_1702_02207_amd import osc, workloads
     w = workloads.c1_paper_two_mass(nsteps=1, out_stride=1)
@@ -463,14 +464,19 @@ def realtime_pass(args):
     out = {"workload": "paper's two-mass system eq. (3), FP64 RK4, one step per period",
            "ticks_per_period": args.rt_ticks, "periods": []}
     try:
-        for period in (20e-6, 100e-6, 1e-3):
-            _log(f"[bench] real-time: period {period * 1e6:.0f} us, {args.rt_ticks} ticks")
-            with osc.Realtime(sysm, x0, v0, 1) as rt:
-                _, _, _, st = rt.run(period, args.rt_ticks, frames=False)
-            out["periods"].append({"period_s": period, "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
-                                   "max_latency_s": st["max_s"], "jitter_s": st["jitter_s"],
-                                   "missed": int(st["missed"]), "gpu_p50_s": st["gpu_p50_s"],
-                                   "launch_p99_s": st["launch_p99_s"]})
+        # "launch": one kernel launch per tick (osc_rt_run); "resident": one
+        # kernel on the device for the whole run, released through host-mapped
+        # memory (osc_rt_run_resident)
+        for mode in ("launch", "resident"):
+            for period in (20e-6, 100e-6, 1e-3):
+                _log(f"[bench] real-time ({mode}): period {period * 1e6:.0f} us, {args.rt_ticks} ticks")
+                with osc.Realtime(sysm, x0, v0, 1) as rt:
+                    run = rt.run if mode == "launch" else rt.run_resident
+                    _, _, _, st = run(period, args.rt_ticks, frames=False)
+                out["periods"].append({"mode": mode, "period_s": period, "p50_latency_s": st["p50_s"],
+                                       "p99_latency_s": st["p99_s"], "max_latency_s": st["max_s"],
+                                       "jitter_s": st["jitter_s"], "missed": int(st["missed"]),
+                                       "gpu_p50_s": st["gpu_p50_s"], "launch_p99_s": st["launch_p99_s"]})
     finally:
         sysm.close()
     return out

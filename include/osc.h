@@ -351,6 +351,30 @@ typedef struct osc_rt_stats {
 osc_status osc_rt_run(osc_rt *rt, double period_s, int64_t nticks, void *x_frames, void *v_frames,
                       double *latencies, osc_rt_stats *stats);
 
+/*
+ * osc_rt_run_resident -- the same periodic loop with one kernel resident on
+ * the device for the whole run instead of one launch per tick (chain handles
+ * only, not damped or driven, not in a propagator mode: OSC_ENOTSUP
+ * otherwise, also when the batch needs more workgroups than the device holds
+ * at once).  At each release the host raises a counter in host-mapped memory;
+ * every workgroup of the kernel polls it, advances its instances one tick,
+ * stores the tick's result (x_frames / v_frames as for osc_rt_run, else the
+ * stepper's own output buffers) and raises a completion count the host polls.
+ * The trajectory is bitwise that of osc_rt_run / osc_rt_tick.  A workgroup
+ * that sees no release for the idle limit (osc_rt_set_idle_limit; default
+ * max(0.1 s, 50 periods)) ends the kernel: the host then returns
+ * OSC_ETIMEOUT, as it does when a tick takes longer than max(10 s, 100
+ * periods).  After any error of this call the stepper's held state is
+ * undefined: later calls on it return OSC_EDEVICE; destroy it.  gpu_p50_s is
+ * 0 (no per-tick events); launch_p99_s is release -> counter raised.
+ */
+osc_status osc_rt_run_resident(osc_rt *rt, double period_s, int64_t nticks, void *x_frames, void *v_frames,
+                               double *latencies, osc_rt_stats *stats);
+
+/* osc_rt_set_idle_limit -- idle limit of osc_rt_run_resident in seconds (> 0;
+ * 0 restores the default). */
+osc_status osc_rt_set_idle_limit(osc_rt *rt, double seconds);
+
 /* osc_rt_destroy -- release the stepper (waits for its queued ticks).  NULL is a no-op. */
 void osc_rt_destroy(osc_rt *rt);
 

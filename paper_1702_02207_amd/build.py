@@ -30,8 +30,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # instance in registers and have DPL independent DOFs at every stage; the
 # register-pressure-first default schedule chains them one DOF at a time
 # (back-to-back dependent instructions), the ILP-first schedule interleaves
-# them (no dependent pair closer than ~10 instructions in the step loop).
-PER_FILE = {"chain.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+# them.  The resident real-time kernels run the same per-lane integrator.
+PER_FILE = {name: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"] for name in ("chain.hip", "resident.hip")}
 
 
 def _compile(src: str, verbose: bool) -> str:

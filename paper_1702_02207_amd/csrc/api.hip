@@ -1009,6 +1009,46 @@ osc_status sys_rt_supported(const osc_sys *s) {
     return OSC_OK;
 }
 
+osc_status sys_rt_resident_supported(const osc_sys *s) {
+    if (s->kind != OSC_CHAIN) return fail(OSC_ENOTSUP, "resident real-time stepping takes chains only");
+    if (s->driven) return fail(OSC_ENOTSUP, "resident real-time stepping: damped or driven chains are not supported");
+    if (s->propagator != 0) return fail(OSC_ENOTSUP, "resident real-time stepping takes the stepping integrators");
+    return OSC_OK;
+}
+
+template <typename T>
+osc_status rt_resident(osc_sys *s, const void *x0, const void *v0, const ResidentSpec &spec, int64_t *blocks) {
+    ChainLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.c = coef_of<T>(s);
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.state = static_cast<T *>(state_buf(s));
+    a.nonfinite = s->flag;
+    ResidentRun<T> r{};
+    r.ctl = spec.ctl;
+    r.first_release = 0;
+    r.nticks = spec.nticks;
+    r.n_start = spec.n0;
+    r.k = spec.k;
+    r.idle_ticks = spec.idle_ticks;
+    r.xf = static_cast<T *>(spec.xf);
+    r.vf = static_cast<T *>(spec.vf);
+    r.xo = static_cast<T *>(spec.xo);
+    r.vo = static_cast<T *>(spec.vo);
+    *blocks = chain_resident_blocks<T>(a, s->cfg);
+    return chain_resident_launch<T>(a, s->method, s->cfg, r, s->stream);
+}
+
+osc_status sys_rt_resident(osc_sys *s, const void *x0, const void *v0, const ResidentSpec &spec, int64_t *blocks) {
+    osc_status r = sys_rt_resident_supported(s);
+    if (r) return r;
+    if ((r = ensure_state(s))) return r;
+    return s->prec == OSC_F32 ? rt_resident<float>(s, x0, v0, spec, blocks)
+                              : rt_resident<double>(s, x0, v0, spec, blocks);
+}
+
 osc_status sys_rt_tick(osc_sys *s, const void *x0, const void *v0, int64_t n0, int64_t k, void *xe, void *ve) {
     osc_status r = sys_rt_supported(s);
     if (r) return r;

@@ -155,6 +155,33 @@ ChainConfig chain_config_at(int i);
 template <typename T>
 osc_status chain_plain(const ChainLaunch<T> &a, int method, hipStream_t st);
 
+// Resident real-time stepping (resident.hip).  The control block lives in
+// host-mapped memory; each field sits on a line of its own.
+struct RtControl {
+    alignas(128) int64_t release;   // host: ticks released so far (negative: stop)
+    alignas(128) uint64_t done;     // device: workgroups that finished a tick, over all ticks
+    alignas(128) int32_t exit_reason;
+};
+constexpr int kRtExitRunning = 0, kRtExitTicks = 1, kRtExitStop = 2, kRtExitIdle = 3;
+template <typename T>
+struct ResidentRun {
+    RtControl *ctl;          // device address of the control block
+    int64_t first_release;   // release count before this run's first tick
+    int64_t nticks;          // ticks of this run
+    int64_t n_start;         // global step at the first tick
+    int64_t k;               // steps per tick
+    int64_t idle_ticks;      // 100 MHz counter ticks without a release before a workgroup gives up
+    T *xf, *vf;              // per-tick outputs [nticks][batch][s], or nullptr
+    T *xo, *vo;              // every tick's output when xf / vf are nullptr
+};
+// Launch the resident kernel (a: the handle's chain launch without step
+// range or outputs).  OSC_ENOTSUP when its workgroups cannot all be resident.
+template <typename T>
+osc_status chain_resident_launch(const ChainLaunch<T> &a, int method, ChainConfig cfg, const ResidentRun<T> &r,
+                                 hipStream_t st);
+template <typename T>
+int64_t chain_resident_blocks(const ChainLaunch<T> &a, ChainConfig cfg);
+
 // ---------------------------------------------------------------------------
 // coefficient preparation, stability bound and energy (prep.hip)
 // ---------------------------------------------------------------------------
@@ -369,6 +396,16 @@ void autotune_apply_cached(osc_sys *s);   // autotune.hip
 // (xe, ve).  OSC_ENOTSUP for paths that keep no per-launch state planes.
 osc_status sys_rt_tick(osc_sys *s, const void *x0, const void *v0, int64_t n0, int64_t k, void *xe, void *ve);
 osc_status sys_rt_supported(const osc_sys *s);
+// Resident stepping of a chain handle: launch the resident kernel for nticks
+// ticks of k steps from global step n0 (outputs as in ResidentRun, untyped);
+// *blocks receives its workgroup count.  OSC_ENOTSUP for other handles.
+struct ResidentSpec {
+    RtControl *ctl;
+    int64_t nticks, n0, k, idle_ticks;
+    void *xf, *vf, *xo, *vo;
+};
+osc_status sys_rt_resident_supported(const osc_sys *s);
+osc_status sys_rt_resident(osc_sys *s, const void *x0, const void *v0, const ResidentSpec &spec, int64_t *blocks);
 
 }  // namespace osc
 

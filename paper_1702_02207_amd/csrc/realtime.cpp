@@ -10,6 +10,10 @@
 // records the latency from release to the result being ready.  A tick is a
 // chunk of the handle's chunked integration from the global step count, so
 // the periodic trajectory is bit for bit that of one osc_integrate call.
+// The resident mode (osc_rt_run_resident, chains) keeps one kernel on the
+// device for the whole run instead (resident.hip): the host raises a release
+// counter in host-mapped memory and polls the kernel's completion count, so a
+// tick costs no launch and no event; both waits are bounded.
 
 #include <algorithm>
 #include <chrono>
@@ -31,6 +35,10 @@ struct osc_rt {
     void *xo = nullptr, *vo = nullptr;   // output of a tick when the caller gives none
     size_t bytes = 0;          // batch * s elements of the handle's type
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    // resident runs: the host-mapped control block (host and device address)
+    osc::RtControl *ctl = nullptr, *ctl_dev = nullptr;
+    double idle_s = 0.0;       // 0: max(0.1 s, 50 periods)
+    bool broken = false;       // a resident run failed part-way: the held state is undefined
 };
 
 namespace {
@@ -43,6 +51,7 @@ void rt_release(osc_rt *rt) {
     if (!rt) return;
     if (rt->sys) (void)hipStreamSynchronize(rt->sys->stream);
     for (void *p : {rt->x0, rt->v0, rt->xo, rt->vo}) pool_free(p);
+    if (rt->ctl) (void)hipHostFree(rt->ctl);
     if (rt->ev_start) (void)hipEventDestroy(rt->ev_start);
     if (rt->ev_end) (void)hipEventDestroy(rt->ev_end);
     delete rt;
@@ -67,6 +76,28 @@ double percentile(std::vector<double> v, double p) {
     const size_t i = (size_t)pos;
     const double f = pos - (double)i;
     return i + 1 < v.size() ? v[i] * (1.0 - f) + v[i + 1] * f : v[i];
+}
+
+osc_rt_stats summarize(const std::vector<double> &lat, const std::vector<double> &launch,
+                       const std::vector<double> &gpu, int64_t missed) {
+    osc_rt_stats o{};
+    o.ticks = (int64_t)lat.size();
+    o.missed = missed;
+    if (!lat.empty()) {
+        double mean = 0.0;
+        for (double v : lat) mean += v;
+        mean /= (double)lat.size();
+        double var = 0.0;
+        for (double v : lat) var += (v - mean) * (v - mean);
+        o.mean_s = mean;
+        o.jitter_s = std::sqrt(var / (double)lat.size());
+        o.p50_s = percentile(lat, 50.0);
+        o.p99_s = percentile(lat, 99.0);
+        o.max_s = *std::max_element(lat.begin(), lat.end());
+        o.launch_p99_s = percentile(launch, 99.0);
+        o.gpu_p50_s = percentile(gpu, 50.0);
+    }
+    return o;
 }
 
 }  // namespace
@@ -111,6 +142,7 @@ osc_status osc_rt_create(osc_sys *sys, const void *x0, const void *v0, int64_t s
 osc_status osc_rt_tick(osc_rt *rt, void *x_out, void *v_out) {
     set_error("");
     if (!rt) return fail(OSC_EINVAL, "stepper is NULL");
+    if (rt->broken) return fail(OSC_EDEVICE, "the stepper's state was lost in a failed resident run; destroy it");
     osc_status r = sys_rt_tick(rt->sys, rt->x0, rt->v0, rt->n, rt->k, x_out ? x_out : rt->xo,
                                v_out ? v_out : rt->vo);
     if (r) return r;
@@ -124,6 +156,7 @@ osc_status osc_rt_run(osc_rt *rt, double period_s, int64_t nticks, void *x_frame
                       double *latencies, osc_rt_stats *stats) {
     set_error("");
     if (!rt) return fail(OSC_EINVAL, "stepper is NULL");
+    if (rt->broken) return fail(OSC_EDEVICE, "the stepper's state was lost in a failed resident run; destroy it");
     if (!(period_s > 0.0 && period_s < 60.0)) return fail(OSC_EINVAL, "period_s must be in (0, 60)");
     if (nticks < 0) return fail(OSC_EINVAL, "nticks must be >= 0");
     const hipStream_t st = rt->sys->stream;
@@ -158,26 +191,95 @@ osc_status osc_rt_run(osc_rt *rt, double period_s, int64_t nticks, void *x_frame
         if (t_done > release + period) ++missed;
         if (latencies) latencies[i] = lat[(size_t)i];
     }
-    if (stats) {
-        osc_rt_stats o{};
-        o.ticks = nticks;
-        o.missed = missed;
-        if (nticks > 0) {
-            double mean = 0.0;
-            for (double v : lat) mean += v;
-            mean /= (double)nticks;
-            double var = 0.0;
-            for (double v : lat) var += (v - mean) * (v - mean);
-            o.mean_s = mean;
-            o.jitter_s = std::sqrt(var / (double)nticks);
-            o.p50_s = percentile(lat, 50.0);
-            o.p99_s = percentile(lat, 99.0);
-            o.max_s = *std::max_element(lat.begin(), lat.end());
-            o.launch_p99_s = percentile(launch, 99.0);
-            o.gpu_p50_s = percentile(gpu, 50.0);
+    if (stats) *stats = summarize(lat, launch, gpu, missed);
+    return OSC_OK;
+}
+
+osc_status osc_rt_set_idle_limit(osc_rt *rt, double seconds) {
+    set_error("");
+    if (!rt) return fail(OSC_EINVAL, "stepper is NULL");
+    if (!(seconds >= 0.0 && seconds < 3600.0)) return fail(OSC_EINVAL, "the idle limit must be in [0, 3600) seconds");
+    rt->idle_s = seconds;
+    return OSC_OK;
+}
+
+osc_status osc_rt_run_resident(osc_rt *rt, double period_s, int64_t nticks, void *x_frames, void *v_frames,
+                               double *latencies, osc_rt_stats *stats) {
+    set_error("");
+    if (!rt) return fail(OSC_EINVAL, "stepper is NULL");
+    if (rt->broken) return fail(OSC_EDEVICE, "the stepper's state was lost in a failed resident run; destroy it");
+    if (!(period_s > 0.0 && period_s < 60.0)) return fail(OSC_EINVAL, "period_s must be in (0, 60)");
+    if (nticks < 0) return fail(OSC_EINVAL, "nticks must be >= 0");
+    osc_status r = sys_rt_resident_supported(rt->sys);
+    if (r) return r;
+    const hipStream_t st = rt->sys->stream;
+    if (!rt->ctl) {
+        void *h = nullptr, *d = nullptr;
+        hipError_t e = hipHostMalloc(&h, sizeof(RtControl), hipHostMallocMapped | hipHostMallocCoherent);
+        if (e != hipSuccess) return fail(OSC_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        if ((e = hipHostGetDevicePointer(&d, h, 0)) != hipSuccess) {
+            (void)hipHostFree(h);
+            return fail(OSC_EDEVICE, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
         }
-        *stats = o;
+        rt->ctl = static_cast<RtControl *>(h);
+        rt->ctl_dev = static_cast<RtControl *>(d);
     }
+    std::vector<double> lat((size_t)nticks), launch((size_t)nticks), gpu((size_t)nticks, 0.0);
+    int64_t missed = 0;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(OSC_EDEVICE, "hipStreamSynchronize failed");
+    if (nticks > 0) {
+        RtControl *c = rt->ctl;
+        __atomic_store_n(&c->release, (int64_t)0, __ATOMIC_SEQ_CST);
+        __atomic_store_n(&c->done, (uint64_t)0, __ATOMIC_SEQ_CST);
+        __atomic_store_n(&c->exit_reason, kRtExitRunning, __ATOMIC_SEQ_CST);
+        const double idle = rt->idle_s > 0.0 ? rt->idle_s : std::max(0.1, 50.0 * period_s);
+        ResidentSpec spec{rt->ctl_dev, nticks, rt->n, rt->k, (int64_t)(idle * 1e8),
+                          x_frames, v_frames, rt->xo, rt->vo};
+        int64_t blocks = 0;
+        if ((r = sys_rt_resident(rt->sys, rt->x0, rt->v0, spec, &blocks))) return r;   // nothing launched
+        // from here on the kernel runs: every way out stops it and waits for it
+        auto abort_run = [&](osc_status code, const std::string &msg) {
+            __atomic_store_n(&c->release, (int64_t)-1, __ATOMIC_SEQ_CST);
+            (void)hipStreamSynchronize(st);
+            rt->broken = true;
+            return fail(code, msg);
+        };
+        const auto period = std::chrono::duration_cast<clock_type::duration>(std::chrono::duration<double>(period_s));
+        const auto t0 = clock_type::now() + period;
+        const double cap = std::max(10.0, 100.0 * period_s);
+        for (int64_t i = 0; i < nticks; ++i) {
+            const auto release = t0 + i * period;
+            for (auto now = clock_type::now(); now < release; now = clock_type::now()) {
+                if (release - now > std::chrono::microseconds(300))
+                    std::this_thread::sleep_for(release - now - std::chrono::microseconds(200));
+            }
+            __atomic_store_n(&c->release, i + 1, __ATOMIC_SEQ_CST);
+            const auto t_raised = clock_type::now();
+            const uint64_t want = (uint64_t)(i + 1) * (uint64_t)blocks;
+            while (__atomic_load_n(&c->done, __ATOMIC_ACQUIRE) < want) {
+                const int reason = __atomic_load_n(&c->exit_reason, __ATOMIC_ACQUIRE);
+                if (reason == kRtExitIdle)
+                    return abort_run(OSC_ETIMEOUT, "the resident kernel reached its idle limit before a release");
+                if (reason == kRtExitStop)
+                    return abort_run(OSC_EDEVICE, "the resident kernel ended before the run's last tick");
+                if (seconds(clock_type::now() - t_raised) > cap)
+                    return abort_run(OSC_ETIMEOUT, "a resident real-time tick did not complete");
+            }
+            const auto t_done = clock_type::now();
+            lat[(size_t)i] = seconds(t_done - release);
+            launch[(size_t)i] = seconds(t_raised - release);
+            if (t_done > release + period) ++missed;
+            if (latencies) latencies[i] = lat[(size_t)i];
+        }
+        __atomic_store_n(&c->release, (int64_t)-1, __ATOMIC_SEQ_CST);
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            rt->broken = true;
+            return fail(OSC_EDEVICE, std::string("resident run: ") + hipGetErrorString(e));
+        }
+        rt->n += nticks * rt->k;
+    }
+    if (stats) *stats = summarize(lat, launch, gpu, missed);
     return OSC_OK;
 }
 

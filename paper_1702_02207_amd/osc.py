@@ -91,6 +91,8 @@ def load():
         "osc_rt_tick": (i32, [vp, vp, vp]),
         "osc_rt_steps": (i64, [vp]),
         "osc_rt_run": (i32, [vp, ctypes.c_double, i64, vp, vp, vp, ctypes.POINTER(RtStats)]),
+        "osc_rt_run_resident": (i32, [vp, ctypes.c_double, i64, vp, vp, vp, ctypes.POINTER(RtStats)]),
+        "osc_rt_set_idle_limit": (i32, [vp, ctypes.c_double]),
         "osc_rt_destroy": (None, [vp]),
         "osc_set_config": (i32, [vp, i32, i64]),
         "osc_autotune": (i32, [vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]),
@@ -390,21 +392,34 @@ class Realtime:
         _check(load().osc_rt_tick(self.handle, _dptr(x), _dptr(v)))
         return x, v
 
-    def run(self, period_s: float, nticks: int, frames: bool = True):
-        """osc_rt_run: returns (x_frames, v_frames, latencies [s], stats dict);
-        frames are the states after each tick, [nticks, batch, s]."""
+    def _run(self, fn, period_s: float, nticks: int, frames: bool):
         import torch
         sysm = self.system
+        if nticks < 0:
+            raise ValueError("nticks must be >= 0")
         xf = vf = None
         if frames and nticks > 0:
             xf = torch.empty((nticks, sysm.batch, sysm.s), dtype=sysm.dtype, device="cuda")
             vf = torch.empty_like(xf)
         lat = np.zeros(max(nticks, 1))
         st = RtStats()
-        _check(load().osc_rt_run(self.handle, float(period_s), int(nticks), _dptr(xf), _dptr(vf),
-                                 lat.ctypes.data, ctypes.byref(st)))
+        _check(fn(self.handle, float(period_s), int(nticks), _dptr(xf), _dptr(vf), lat.ctypes.data, ctypes.byref(st)))
         stats = {name: getattr(st, name) for name, _ in RtStats._fields_}
         return xf, vf, lat[:nticks], stats
+
+    def run(self, period_s: float, nticks: int, frames: bool = True):
+        """osc_rt_run: returns (x_frames, v_frames, latencies [s], stats dict);
+        frames are the states after each tick, [nticks, batch, s]."""
+        return self._run(load().osc_rt_run, period_s, nticks, frames)
+
+    def run_resident(self, period_s: float, nticks: int, frames: bool = True):
+        """osc_rt_run_resident: the same loop with one kernel resident on the
+        device for the whole run (chains); same return values."""
+        return self._run(load().osc_rt_run_resident, period_s, nticks, frames)
+
+    def set_idle_limit(self, seconds: float):
+        """osc_rt_set_idle_limit (0 restores the default)."""
+        _check(load().osc_rt_set_idle_limit(self.handle, float(seconds)))
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -142,3 +142,127 @@ def test_realtime_rejects_unsupported_paths():
         assert e.value.status == osc.OSC_ENOTSUP
     finally:
         sysm.close()
+
+
+@pytest.mark.parametrize("case", ["chain_f32", "chain_verlet", "chain_long", "chain_f64", "two_wave_chain"])
+def test_resident_ticks_are_the_frames_of_one_integration(case):
+    """osc_rt_run_resident: one kernel stays on the device and advances one
+    tick per release; its frames are bit for bit those of osc_integrate, also
+    when launch-mode ticks come before and after it."""
+    import torch
+    k, n_before, n_res, n_after = 5, 3, 30, 2
+    s = {"chain_long": 1024, "two_wave_chain": 1500}.get(case, 8)
+    m, kk, dt, x0, v0 = _chain(2000 + len(case), 6, s)
+    method = "verlet" if case == "chain_verlet" else "rk4"
+    prec = "f64" if case == "chain_f64" else "f32"
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    sysm = osc.System("chain", method, prec, m, kk, dt).create()
+    X0, V0 = to_dev(x0, dtype), to_dev(v0, dtype)
+    try:
+        total = n_before + n_res + n_after
+        ref_x, ref_v = _integrate_frames(sysm, X0, V0, total, k)
+        with osc.Realtime(sysm, X0, V0, k) as rt:
+            bx, bv = _ticks(rt, n_before)
+            xf, vf, lat, stats = rt.run_resident(200e-6, n_res)
+            assert rt.steps == (n_before + n_res) * k
+            ax, av = _ticks(rt, n_after)
+            xf, vf = xf.cpu().numpy(), vf.cpu().numpy()
+    finally:
+        sysm.close()
+    got_x = np.concatenate([bx, xf, ax])
+    got_v = np.concatenate([bv, vf, av])
+    np.testing.assert_array_equal(got_x, ref_x)
+    np.testing.assert_array_equal(got_v, ref_v)
+    assert stats["ticks"] == n_res and len(lat) == n_res and np.all(lat > 0)
+
+
+def test_resident_loop_on_the_paper_system():
+    """The paper's two-mass system (eq. (3), FP64), one step per 50 us period in
+    the resident mode: the trajectory equals osc_integrate bit for bit and
+    the closed-form normal-mode solution within 1e-10."""
+    import torch
+    w = workloads.c1_paper_two_mass(nsteps=2000, out_stride=1)
+    sysm = osc.System("chain", "rk4", "f64", w.m, w.k, w.dt).create()
+    x0, v0 = to_dev(w.x0, torch.float64), to_dev(w.v0, torch.float64)
+    try:
+        ref_x, ref_v = _integrate_frames(sysm, x0, v0, 2000, 1)
+        with osc.Realtime(sysm, x0, v0, 1) as rt:
+            _, _, _, launched = rt.run(50e-6, 2000, frames=False)
+        with osc.Realtime(sysm, x0, v0, 1) as rt:
+            xf, vf, lat, stats = rt.run_resident(50e-6, 2000)
+            xf, vf = xf.cpu().numpy(), vf.cpu().numpy()
+    finally:
+        sysm.close()
+    np.testing.assert_array_equal(xf, ref_x)
+    np.testing.assert_array_equal(vf, ref_v)
+    t = np.arange(1, 2001) * w.dt[0]
+    xr, vr = cf.two_mass_equal(t, 2.0, 2025.0, w.x0[0], w.v0[0])
+    assert oracle.rel_traj_err(xf, xr[:, None, :])[0] < 1e-10
+    assert stats["ticks"] == 2000 and np.all(lat > 0)
+    print(f"paper system, 50 us period: resident p50 {stats['p50_s'] * 1e6:.1f} us p99 {stats['p99_s'] * 1e6:.1f} us "
+          f"missed {stats['missed']}; one launch per tick p50 {launched['p50_s'] * 1e6:.1f} us "
+          f"p99 {launched['p99_s'] * 1e6:.1f} us missed {launched['missed']}")
+
+
+def test_resident_rejects_unsupported_handles():
+    import torch
+    rng = np.random.default_rng(2010)
+    M, K = workloads.random_dense_system(rng, 40)
+    dt = np.array([0.01 / workloads.dense_omega_max(M, K)])
+    sysm = osc.System("dense", "rk4", "f32", M, K, dt, shared=True, batch=4).create()
+    x0 = to_dev(rng.normal(size=(4, 40)), torch.float32)
+    try:
+        with osc.Realtime(sysm, x0, x0, 1) as rt:
+            with pytest.raises(osc.OscError) as e:
+                rt.run_resident(1e-3, 2)
+            assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        sysm.close()
+    m, k, dt, x0, v0 = _chain(2011, 4, 8)
+    sysm = osc.System("chain", "rk4", "f32", m, k, dt).create()
+    X0 = to_dev(x0, torch.float32)
+    try:
+        sysm.set_excitation(0.1, 0.0, None)
+        with osc.Realtime(sysm, X0, X0, 1) as rt:
+            with pytest.raises(osc.OscError) as e:
+                rt.run_resident(1e-3, 2)
+            assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        sysm.close()
+    # more workgroups than the device holds at once: refused before any launch
+    w = workloads.c2_two_dof_ensemble(batch=1 << 20, nsteps=10)
+    sysm = osc.System("chain", "rk4", "f32", w.m, w.k, w.dt).create()
+    X0 = to_dev(w.x0, torch.float32)
+    try:
+        with osc.Realtime(sysm, X0, X0, 1) as rt:
+            with pytest.raises(osc.OscError) as e:
+                rt.run_resident(1e-3, 2)
+            assert e.value.status == osc.OSC_ENOTSUP
+            rt.tick()   # the stepper is unharmed
+    finally:
+        sysm.close()
+
+
+def test_resident_idle_limit_ends_the_kernel():
+    """A release that comes later than the idle limit: every workgroup gives
+    up and the kernel ends on its own; the call reports OSC_ETIMEOUT, the
+    stepper refuses further use, and a new stepper runs normally."""
+    import torch
+    m, k, dt, x0, v0 = _chain(2012, 6, 8)
+    sysm = osc.System("chain", "rk4", "f32", m, k, dt).create()
+    X0, V0 = to_dev(x0, torch.float32), to_dev(v0, torch.float32)
+    try:
+        with osc.Realtime(sysm, X0, V0, 3) as rt:
+            rt.set_idle_limit(1e-3)
+            with pytest.raises(osc.OscError) as e:
+                rt.run_resident(50e-3, 3)
+            assert e.value.status == osc.OSC_ETIMEOUT
+            with pytest.raises(osc.OscError) as e:
+                rt.tick()
+            assert e.value.status == osc.OSC_EDEVICE
+        ref_x, _ = _integrate_frames(sysm, X0, V0, 4, 3)
+        with osc.Realtime(sysm, X0, V0, 3) as rt:
+            xf, _, _, _ = rt.run_resident(1e-3, 4)
+            np.testing.assert_array_equal(xf.cpu().numpy(), ref_x)
+    finally:
+        sysm.close()
