@@ -210,9 +210,10 @@ def cpu_baseline(w, kind, method, prec, idx):
 def jump_roofline(w, kind, seconds):
     """Frame jumps: the two-mass ensemble's one kernel moves its inputs, the
     frames and the final state (HBM-bound); dense shared systems are FP64
-    matrix-core products: the powers of the step matrix by repeated squaring
-    (A^2, then squarings and multiplications of 2s x 2s matrices) and one
-    (batch x 2s) x (2s x 2s) product per frame."""
+    matrix-core products (rocBLAS DGEMM): the powers of the step matrix by
+    repeated squaring (A^2, then squarings and multiplications of 2s x 2s
+    matrices) and one (batch x 2s) x (2s x 2s) product per frame; seconds is
+    the device time of the whole call."""
     nf = w.nsteps // w.out_stride + 1 if w.out_stride else 0
     rest = w.nsteps - (nf - 1) * w.out_stride if nf else w.nsteps
     if kind == "chain":
@@ -230,7 +231,7 @@ def jump_roofline(w, kind, seconds):
     flops = 2.0 * w.s ** 3 + gemms * 2.0 * n ** 3 + ((nf - 1) + (rest > 0)) * 2.0 * n * n * w.batch
     achieved = flops / seconds / 1e12
     return dict(bound="mfma", achieved=round(achieved, 2), peak=PEAK["fp64"], unit="TFLOP/s",
-                frac=round(achieved / PEAK["fp64"], 4), traffic=None, kernel="product_kernel (FP64)",
+                frac=round(achieved / PEAK["fp64"], 4), traffic=None, kernel="rocBLAS DGEMM (FP64 matrix cores)",
                 kernel_ms=round(seconds * 1e3, 4), flops_per_launch=flops, matrix_products=gemms)
 
 

@@ -16,10 +16,17 @@
 //     step applies P - I, split into FP32 high and low parts, to the
 //     compensated state, one lane per instance.
 // Systems of s <= 2 keep P in registers, one lane per system; larger ones
-// (s <= 256) use batched FP64 matrix-core products (gemm64).
+// (s <= 256) form P^k and apply it by FP64 matrix-core products: the
+// squarings and the frame jumps are plain GEMMs (row-major n x n by n x n,
+// and batch x n by the transposed n x n), which run through rocBLAS's DGEMM.
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
 #include <type_traits>
+
+#include <rocblas/rocblas.h>
 
 #include "osc_internal.h"
 
@@ -311,15 +318,39 @@ __global__ void __launch_bounds__(kThreads) store_z_kernel(int64_t batch, int s,
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// C = X Y for every system (n x n), C distinct from X and Y.
+// One rocBLAS handle per device, created on first use; calls set the stream
+// and enqueue under the lock (the products run asynchronously on it).
+std::mutex blas_mutex;
+std::map<int, rocblas_handle> blas_handles;
+
+// C = op(A) B in column-major terms (rocBLAS's convention), strided over nsys
+osc_status dgemm(hipStream_t st, bool trans_a, int m, int n, int k, const double *A, int64_t stride_a,
+                 const double *B, int64_t stride_b, double *C, int64_t stride_c, int64_t nsys) {
+    int dev = 0;
+    OSC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(blas_mutex);
+    rocblas_handle &h = blas_handles[dev];
+    if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
+        h = nullptr;
+        return fail(OSC_EDEVICE, "rocblas_create_handle failed");
+    }
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return fail(OSC_EDEVICE, "rocblas_set_stream failed");
+    const double one = 1.0, zero = 0.0;
+    const rocblas_operation ta = trans_a ? rocblas_operation_transpose : rocblas_operation_none;
+    const rocblas_status r =
+        nsys == 1 ? rocblas_dgemm(h, ta, rocblas_operation_none, m, n, k, &one, A, trans_a ? k : m, B, k, &zero, C, m)
+                  : rocblas_dgemm_strided_batched(h, ta, rocblas_operation_none, m, n, k, &one, A, trans_a ? k : m,
+                                                  stride_a, B, k, stride_b, &zero, C, m, stride_c, (rocblas_int)nsys);
+    if (r != rocblas_status_success)
+        return fail(OSC_EDEVICE, std::string("rocBLAS DGEMM: ") + rocblas_status_to_string(r));
+    return OSC_OK;
+}
+
+// C = X Y for every system (row-major n x n), C distinct from X and Y: in
+// column-major terms C^T = Y^T X^T.
 osc_status square_mul(int64_t nsys, int n, const double *X, const double *Y, double *C, hipStream_t st) {
-    Gemm64 g{};
-    g.m = g.n = g.k = n;
-    g.overwrite = 1;
-    g.A = X, g.a_i = n, g.a_p = 1, g.a_sys = (size_t)n * n;
-    g.B = Y, g.b_p = n, g.b_j = 1, g.b_sys = (size_t)n * n;
-    g.C = C, g.c_i = n, g.c_j = 1, g.c_sys = (size_t)n * n;
-    return gemm64(g, nsys, st);
+    const int64_t nn = (int64_t)n * n;
+    return dgemm(st, false, n, n, n, Y, nn, X, nn, C, nn, nsys);
 }
 
 // Temporaries of one call: returned to the pool only after the stream has
@@ -655,25 +686,11 @@ osc_status propagator_jump(const PropArgs &a, int s, const PropRun<T> &run, hipS
     }
     hipLaunchKernelGGL((load_z_kernel<T>), dim3(blocks_for(run.batch * s)), dim3(kThreads), 0, st, run, s, Z);
     OSC_HIP(hipGetLastError());
-    // Z' = Z P^T, one row per instance
+    // Z' = Z P^T, one row per instance: column-major Z'^T = P Z^T, with the
+    // row-major P read as its transpose
     auto advance = [&](const double *P) -> osc_status {
-        Gemm64 g{};
-        g.overwrite = 1;
-        g.n = g.k = n;
-        g.b_p = 1, g.b_j = n;
-        g.c_i = n, g.c_j = 1;
-        g.a_i = n, g.a_p = 1;
-        g.A = Z, g.B = P, g.C = Z2;
-        int64_t nsys = 1;
-        if (a.nsys == 1) {
-            g.m = (int)run.batch;
-        } else {
-            g.m = 1;
-            g.a_sys = g.c_sys = n;
-            g.b_sys = nn;
-            nsys = run.batch;
-        }
-        osc_status e = gemm64(g, nsys, st);
+        osc_status e = a.nsys == 1 ? dgemm(st, true, n, (int)run.batch, n, P, 0, Z, 0, Z2, 0, 1)
+                                   : dgemm(st, true, n, 1, n, P, (int64_t)nn, Z, n, Z2, n, run.batch);
         if (e) return e;
         std::swap(Z, Z2);
         return OSC_OK;
