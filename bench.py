@@ -5,8 +5,8 @@ Default workload (c3): 4096 fixed-free spring chains of s = 1024 bodies
 (eq. (2) generalised), masses U[0.5, 2], springs LogU[1e2, 1e4],
 x0 ~ N(0, sigma = 0.1), v0 = 0, dt = 0.01/omega_max per chain, 10^5 classic
 RK4 steps with FP32 state (synthetic, seeded): the largest configuration
-that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c4, c4v, c5;
-and the propagator modes: c2p, the per-step step matrix; c2j and c4j, frames
+that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c3d, c4, c4v, c5;
+and the propagator modes: c1p and c2p, the per-step step matrix; c2j and c4j, frames
 by powers of the step matrix).
 
 One timed step is one pass of the whole hot path over the batch, with every
@@ -63,7 +63,7 @@ DENSE_PRODUCTS = {"rk4": 4, "verlet": 1}
 DENSE_HW_TERMS = {"rk4": 7, "verlet": 3}     # MFMA products per step with the FP16 splits
 
 # oracle sample sizes (instance 0, the last instance and seeded others)
-CPU_SAMPLE = {"c1": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c3d": 32,
+CPU_SAMPLE = {"c1": 1, "c1p": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c3d": 32,
               "c4": 256, "c4v": 256, "c4j": 256}
 # the per-step propagator's own count for two-mass RK4 at FP32: per DOF, dx
 # from the low parts, the w terms and the high parts of one row of the 4x4
@@ -96,6 +96,9 @@ WORKLOADS = {
                desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, FP32 state, FP16x3 MFMA"),
     "c4v": dict(kind="dense", method="verlet", prec="f32",
                 desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 Verlet steps, FP32 state, FP16x3 MFMA"),
+    "c1p": dict(kind="chain", method="rk4", prec="f64", propagator=2,
+                desc="paper's two-mass system eq. (3): m=2, C=2025, dt=1e-5, 1e5 RK4 steps, FP64, 1 instance, "
+                     "per-step propagator (the 4x4 step matrix)"),
     "c2p": dict(kind="chain", method="rk4", prec="f32", propagator=2,
                 desc="two-mass ensemble eq. (2): 2^20 instances, s=2, 1e4 RK4 steps, FP32, "
                      "per-step propagator (one 4x4 step matrix per instance)"),
@@ -119,7 +122,7 @@ def _log(msg):
 
 def make_workload(name):
     from paper_1702_02207_amd import workloads
-    if name == "c1":
+    if name in ("c1", "c1p"):
         return workloads.c1_paper_two_mass(out_stride=1000)
     if name.startswith("c2"):
         w = workloads.c2_two_dof_ensemble()
