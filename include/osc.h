@@ -194,7 +194,9 @@ osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double 
  * unit time), required with F.  Dense systems take f = M^-1 F on the GPU (FP64,
  * by the Cholesky factor of M).  alpha = beta = 0 and F = NULL make the
  * handle free again.  Afterwards osc_integrate (and osc_integrate_static) run
- * the damped / driven integrator (one workgroup per instance; s <= 2048);
+ * the damped / driven integrator: chains of s <= 1024 in registers, one
+ * operator shared by many instances (FP32, s <= 256) on the matrix cores, the
+ * others one workgroup per instance (s <= 2048);
  * osc_integrate_plain and the propagator modes return OSC_ENOTSUP; osc_energy
  * still returns 1/2 v^T M v + 1/2 x^T K x (no longer conserved).
  * OSC_ENOTSUP for a Verlet handle (the velocity-dependent force would make the
@@ -242,6 +244,9 @@ osc_status osc_dense_operator(osc_sys *sys, double *A);
  *                             many workgroups; for few instances of large s).
  *                             Damped / driven chains: 0 automatic (registers
  *                             for s <= 1024), 1 one workgroup per instance.
+ *                             Damped / driven dense systems: 0 and 2 the
+ *                             matrix cores where MFMA applies, 1 one
+ *                             workgroup per instance.
  *   OSC_CFG_STEPS_PER_LAUNCH  maximum time steps per kernel launch (0 = the
  *                             whole run).  The state between launches keeps its
  *                             compensation terms, so chunked and unchunked runs

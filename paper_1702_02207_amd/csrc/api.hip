@@ -597,6 +597,34 @@ osc_status integrate_driven(osc_sys *s, const void *x0, const void *v0, int64_t 
                             void *xf, void *vf, void *xe, void *ve) {
     if (s->propagator)
         return fail(OSC_ENOTSUP, "the propagator modes take free (undamped, undriven) systems");
+    if constexpr (std::is_same<T, float>::value) {
+        // one operator shared by many instances: the matrix-core integrator
+        if (s->kind == OSC_DENSE && s->shared && use_mfma(s)) {
+            DenseMfmaLaunch a{};
+            a.batch = s->batch;
+            a.s = s->s;
+            a.B1 = s->F1;
+            a.B2 = s->F2;
+            a.inv_beta = s->inv_beta;
+            a.h = s->h_shared;
+            a.alpha = s->alpha;
+            a.beta = s->beta;
+            a.f = s->force;
+            a.omega = s->omega;
+            a.x0 = static_cast<const float *>(x0);
+            a.v0 = static_cast<const float *>(v0);
+            a.out_stride = out_stride;
+            a.frame_plane = s->batch * (int64_t)s->s;
+            a.xf = static_cast<float *>(xf);
+            a.vf = static_cast<float *>(vf);
+            a.xe = static_cast<float *>(xe);
+            a.ve = static_cast<float *>(ve);
+            a.nonfinite = s->flag;
+            const int method = kMfmaDriven + (s->beta != 0.0 ? 1 : 0) + (s->force ? 2 : 0);
+            return run_chunks(s, a, nsteps,
+                              [&](const DenseMfmaLaunch &c) { return dense_mfma_launch(c, method, s->stream); });
+        }
+    }
     DrivenLaunch<T> a{};
     a.kind = s->kind;
     a.batch = s->batch;
@@ -824,7 +852,7 @@ osc_status osc_integrate_static(osc_sys *s, const void *x0, const void *v0, int6
     if (s->propagator == 1 && !propagator_small(s->s) && !s->driven)
         return fail(OSC_ENOTSUP, "osc_integrate_static: frame jumps of systems with s > 2 form their matrix powers "
                                  "in per-call buffers; use osc_integrate");
-    if (s->propagator == 0 && s->kind == OSC_DENSE && use_mfma(s) && !s->shared)
+    if (s->propagator == 0 && s->kind == OSC_DENSE && use_mfma(s) && !s->shared && !s->driven)
         return fail(OSC_ENOTSUP, "osc_integrate_static: per-instance operators on the matrix cores take a work "
                                  "list built per call; use osc_integrate");
     if (s->driven) {

@@ -30,6 +30,25 @@
 // 2^-11 (h omega)^2 / 12.  The state of each
 // instance is scaled by a power of two sigma so that |x| < 1 in FP16 terms;
 // powers of two keep every scaling exact.
+//
+// Damped, driven systems (method kMfmaDriven + EX, RK4 only) take the RK4
+// map as the four-level recursion y_{n+1} = y + z1 + z2/2 + z3/6 + z4/24,
+// z1 = L y + g1 e, z_k = L z_{k-1} + g_k e (L y = (w, -Bx - a w - b Bw),
+// a = alpha h, b = beta / h, e = (0, h^2 f), g = (c0, 2 (ch - c0), 0,
+// 4 (c0 - 2 ch + c1)) from the force phases at t_n, t_n + h/2, t_n + h).  The
+// x-part of each level is the previous level's w-part, so the products are
+// B x (three terms), B w (two; three with stiffness damping, whose b B w
+// enters the first level), then B of the level w-parts (one term each: they
+// enter at third order and beyond, like B P and B Q above).  The level
+// w-parts are kept scaled by powers of beta (Z1 = beta sigma z1, Z2 = beta
+// sigma z2, Z3 = beta^2 sigma z3, Z4 = beta^2 sigma z4) so that every FP16
+// operand is of order one:
+//   Z1 = -B^x - a beta w - b B^w + g1 F,   Z2 = -B^w - a Z1 - b ib B^Z1 + g2 F,
+//   Z3 = -B^Z1 - a beta Z2 - b B^Z2,        Z4 = -B^Z2 - a Z3 - b ib B^Z3 + beta g4 F,
+// with F = beta sigma h^2 f (kept in LDS) and ib = 1 / beta, and
+//   sigma dx = w + ib (Z1/2 + Z2/6 + ib Z3/24),
+//   sigma dw = ib (Z1 + Z2/2 + ib (Z3/6 + Z4/24)).
+// The force's phase is the FP64 rotation of the other driven kernels.
 
 #include <cstdint>
 
@@ -60,13 +79,17 @@ __device__ __forceinline__ f4 mfma(half8 a, half8 b, f4 c) {
 // One workgroup's share of launch a: the 16 instances of column tile `tile`.
 template <int RT, int NW, int METHOD>
 __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t tile) {
+    constexpr bool DRIVEN = METHOD >= kMfmaDriven;
+    constexpr bool BETA = DRIVEN && (METHOD & 1), FORCED = DRIVEN && (METHOD & 2);
     constexpr int kNW = NW;          // waves per workgroup
     constexpr int SP = 16 * RT * NW; // padded dimension
     constexpr int KS = SP / 32;      // k-steps of 32
     constexpr int NB = SP / 8;       // 8-row blocks of an operand
     // operand buffers: x (hi, lo), w (hi), B x (hi), B w (hi)
     __shared__ __attribute__((aligned(16))) _Float16 bufA[2][NB][kNC][8];
-    __shared__ __attribute__((aligned(16))) _Float16 bufB[1][NB][kNC][8];
+    // w takes its low plane too where the stiffness damping b B w enters the
+    // first level (driven launches with beta != 0)
+    __shared__ __attribute__((aligned(16))) _Float16 bufB[BETA ? 2 : 1][NB][kNC][8];
     __shared__ __attribute__((aligned(16))) _Float16 bufC[1][NB][kNC][8];
     __shared__ __attribute__((aligned(16))) _Float16 bufD[1][NB][kNC][8];
     __shared__ float smax[kNW][kNC];
@@ -124,6 +147,23 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
             }
             mx = fmax(mx, fmax(fabs((double)x[t][r]), fabs((double)w[t][r])));
         }
+    // the force, beta h^2 f (scaled by sigma below), in lane-private LDS
+    // slots beside the compensation terms; its size joins the scale choice,
+    // as the forced response grows from it
+    __shared__ float sfs[kNW][RT][4][64];
+    float(&Fs)[RT][4][64] = sfs[wave];
+    const double beta_d = 1.0 / (double)ib;
+    if constexpr (FORCED) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + 16 * t + 4 * quad + r;
+                const double fd = (active && row < s) ? beta_d * h * h * a.f[base + row] : 0.0;
+                Fs[t][r][lane] = (float)fd;
+                mx = fmax(mx, fabs(fd));
+            }
+    }
     // per-instance power-of-two scale sigma (max |state| sigma in [0.5, 1)),
     // chosen from the initial state and carried with the state across
     // launches so that chunked runs round exactly like unchunked ones
@@ -149,7 +189,12 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
             xl[t][r][lane] *= sigma;
             w[t][r] *= sigma;
             wl[t][r][lane] *= sigma;
+            if constexpr (FORCED) Fs[t][r][lane] *= sigma;
         }
+    Phase ph{};
+    if (FORCED && active) ph.start(a.omega[b] * h, a.n0);
+    const float ka = (float)(a.alpha * h), kab = (float)(a.alpha * h * beta_d);
+    const float kb = (float)(a.beta / h), kbi = (float)(a.beta / h * (double)ib);
 
     // operand u -> LDS (hi plane, optionally the scaled low plane)
     auto put = [&](_Float16 (*buf)[NB][kNC][8], const float (&u)[RT][4], bool two) {
@@ -301,7 +346,85 @@ __device__ __forceinline__ void mfma_run(const DenseMfmaLaunch &a, const int64_t
             stop = nf < stop ? nf : stop;
         }
         for (int64_t it = n; it < stop; ++it) {
-            if constexpr (METHOD == OSC_RK4) {
+            if constexpr (DRIVEN) {
+                float g1 = 0.0f, g2 = 0.0f, gb4 = 0.0f;
+                if constexpr (FORCED) {
+                    if (it % kAnchor == 0) ph.set(it);
+                    const double c0 = ph.c;
+                    ph.half();
+                    const double ch = ph.c;
+                    ph.half();
+                    const double c1 = ph.c;
+                    g1 = (float)c0;
+                    g2 = (float)(2.0 * (ch - c0));
+                    gb4 = (float)(4.0 * ((c0 - ch) + (c1 - ch)) * beta_d);
+                }
+                float pk[RT][4], qk[RT][4], Z[RT][4], R[RT][4], sx[RT][4], sw[RT][4];
+                __syncthreads();
+                put(bufA, x, true);
+                put(bufB, w, BETA);
+                __syncthreads();
+                prod3(bufA, pk);   // B^ x
+                if constexpr (BETA) prod3(bufB, qk);   // B^ w, also in b B^ w at the first level
+                else prod2(bufB, qk);
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float z = __builtin_fmaf(-kab, w[t][r], -pk[t][r]);
+                        if constexpr (BETA) z = __builtin_fmaf(-kb, qk[t][r], z);
+                        if constexpr (FORCED) z = __builtin_fmaf(Fs[t][r][lane], g1, z);
+                        Z[t][r] = z;   // Z1
+                        sx[t][r] = 0.5f * z;
+                        sw[t][r] = z;
+                    }
+                put(bufC, Z, false);
+                __syncthreads();
+                prod1(bufC, R);   // B^ Z1
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float z = __builtin_fmaf(-ka, Z[t][r], -qk[t][r]);
+                        if constexpr (BETA) z = __builtin_fmaf(-kbi, R[t][r], z);
+                        if constexpr (FORCED) z = __builtin_fmaf(Fs[t][r][lane], g2, z);
+                        Z[t][r] = z;   // Z2
+                        pk[t][r] = R[t][r];   // B^ Z1
+                        sx[t][r] = __builtin_fmaf(1.0f / 6.0f, z, sx[t][r]);
+                        sw[t][r] = __builtin_fmaf(0.5f, z, sw[t][r]);
+                    }
+                put(bufD, Z, false);
+                __syncthreads();
+                prod1(bufD, R);   // B^ Z2
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float z = __builtin_fmaf(-kab, Z[t][r], -pk[t][r]);
+                        if constexpr (BETA) z = __builtin_fmaf(-kb, R[t][r], z);
+                        Z[t][r] = z;   // Z3
+                        qk[t][r] = R[t][r];   // B^ Z2
+                    }
+                if constexpr (BETA) {
+                    put(bufC, Z, false);
+                    __syncthreads();
+                    prod1(bufC, R);   // B^ Z3
+                }
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float z = __builtin_fmaf(-ka, Z[t][r], -qk[t][r]);
+                        if constexpr (BETA) z = __builtin_fmaf(-kbi, R[t][r], z);
+                        if constexpr (FORCED) z = __builtin_fmaf(Fs[t][r][lane], gb4, z);   // Z4
+                        const float dxs = __builtin_fmaf(ib, __builtin_fmaf(ib * (1.0f / 24.0f), Z[t][r], sx[t][r]),
+                                                         w[t][r]);
+                        const float dws = ib * __builtin_fmaf(ib, __builtin_fmaf(1.0f / 24.0f, z, (1.0f / 6.0f) * Z[t][r]),
+                                                              sw[t][r]);
+                        comp_add(x[t][r], xl[t][r][lane], dxs);
+                        comp_add(w[t][r], wl[t][r][lane], dws);
+                    }
+            } else if constexpr (METHOD == OSC_RK4) {
                 // each product is folded into the partial sums and written out
                 // as the next operand as soon as it is formed; P, sx and sw
                 // stay live until the increments are complete
@@ -424,10 +547,26 @@ __global__ void dense_mfma_fragments_kernel(int s, int sp, const double *__restr
 template <int RT, int NW>
 void launch_rt(const DenseMfmaLaunch &a, int method, hipStream_t st) {
     const unsigned blocks = (unsigned)((a.batch + kNC - 1) / kNC);
-    if (method == OSC_RK4)
-        hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_RK4>), dim3(blocks), dim3(64 * NW), 0, st, a);
-    else
-        hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_VERLET>), dim3(blocks), dim3(64 * NW), 0, st, a);
+    switch (method) {
+        case OSC_RK4:
+            hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_RK4>), dim3(blocks), dim3(64 * NW), 0, st, a);
+            break;
+        case OSC_VERLET:
+            hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, OSC_VERLET>), dim3(blocks), dim3(64 * NW), 0, st, a);
+            break;
+        case kMfmaDriven + 0:
+            hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, kMfmaDriven + 0>), dim3(blocks), dim3(64 * NW), 0, st, a);
+            break;
+        case kMfmaDriven + 1:
+            hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, kMfmaDriven + 1>), dim3(blocks), dim3(64 * NW), 0, st, a);
+            break;
+        case kMfmaDriven + 2:
+            hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, kMfmaDriven + 2>), dim3(blocks), dim3(64 * NW), 0, st, a);
+            break;
+        default:
+            hipLaunchKernelGGL((dense_mfma_kernel<RT, NW, kMfmaDriven + 3>), dim3(blocks), dim3(64 * NW), 0, st, a);
+            break;
+    }
 }
 
 template <int RT, int NW>
@@ -475,6 +614,8 @@ osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *
 
 osc_status dense_mfma_launch(const DenseMfmaLaunch &a, int method, hipStream_t st) {
     if (a.batch == 0) return OSC_OK;
+    if (method != OSC_RK4 && method != OSC_VERLET && (method < kMfmaDriven || method > kMfmaDriven + 3))
+        return fail(OSC_EINVAL, "unknown MFMA method");
     if ((a.batch + kNC - 1) / kNC > 0x7fffffff) return fail(OSC_EINVAL, "batch too large for one launch");
     // 32 rows per wave: the operator takes 128 registers per lane, which
     // leaves room for two waves per SIMD

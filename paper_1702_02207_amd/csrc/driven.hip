@@ -31,7 +31,6 @@ namespace osc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int64_t kAnchor = 64;
 
 template <typename T>
 __device__ __forceinline__ void comp_add(T &hi, T &lo, T y) {
@@ -44,24 +43,6 @@ __device__ __forceinline__ void comp_add(T &hi, T &lo, T y) {
         hi = hi + y;
     }
 }
-
-// cos / sin of the force's phase at the current half step
-struct Phase {
-    double c, s;     // e^{i Omega h tau}
-    double rc, rs;   // e^{i Omega h / 2}
-    double wh;       // Omega h
-    __device__ void set(int64_t n) {
-        sincos(wh * (double)n, &s, &c);
-    }
-    // The rounding is spelled out (one product, then one fused
-    // multiply-add) so that every inlined copy, in and out of the step loop,
-    // computes bit for bit the same rotation.
-    __device__ void half() {
-        const double nc = __builtin_fma(c, rc, -(s * rs)), ns = __builtin_fma(s, rc, c * rs);
-        c = nc;
-        s = ns;
-    }
-};
 
 template <typename T, int RPT, int KIND>
 __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
@@ -143,17 +124,7 @@ __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
 
     Phase ph{};
     const bool forced = a.f != nullptr;
-    if (forced) {
-        const double wh = a.omega[b] * h;
-        ph.wh = wh;
-        sincos(0.5 * wh, &ph.rs, &ph.rc);
-        const int64_t anchor = a.n0 - a.n0 % kAnchor;
-        ph.set(anchor);
-        for (int64_t q = anchor; q < a.n0; ++q) {
-            ph.half();
-            ph.half();
-        }
-    }
+    if (forced) ph.start(a.omega[b] * h, a.n0);
 
     auto write_frame = [&](int64_t f, bool initial) {
         const size_t fo = (size_t)f * plane;
@@ -422,17 +393,7 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     };
 
     Phase ph{};
-    if (forced && active) {
-        const double wh = a.omega[b] * h;
-        ph.wh = wh;
-        sincos(0.5 * wh, &ph.rs, &ph.rc);
-        const int64_t anchor = a.n0 - a.n0 % kAnchor;
-        ph.set(anchor);
-        for (int64_t q = anchor; q < a.n0; ++q) {
-            ph.half();
-            ph.half();
-        }
-    }
+    if (forced && active) ph.start(a.omega[b] * h, a.n0);
     auto xval = [&](int j) { return (T)((double)x[j] + (double)xl[j]); };
     auto vval = [&](int j) { return (T)(((double)w[j] + (double)wl[j]) / h); };
     // the caller's x0 / v0 unchanged (frame 0, nsteps = 0)

@@ -77,6 +77,36 @@ __device__ __forceinline__ double from_right(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Phase of a harmonic force, cos and sin of Omega t at the current half step:
+// set exactly (sincos of Omega h n) at every global step index divisible by
+// kAnchor and advanced by half-step rotations in between, so that chunked and
+// unchunked runs agree bitwise.  The rotation's rounding is spelled out (one
+// product, then one fused multiply-add) so that every inlined copy, in and
+// out of a step loop, computes bit for bit the same values.
+constexpr int64_t kAnchor = 64;
+struct Phase {
+    double c, s;     // e^{i Omega h tau}
+    double rc, rs;   // e^{i Omega h / 2}
+    double wh;       // Omega h
+    __device__ void set(int64_t n) { sincos(wh * (double)n, &s, &c); }
+    __device__ void half() {
+        const double nc = __builtin_fma(c, rc, -(s * rs)), ns = __builtin_fma(s, rc, c * rs);
+        c = nc;
+        s = ns;
+    }
+    // ready for the step that starts at global step n0
+    __device__ void start(double omega_h, int64_t n0) {
+        wh = omega_h;
+        sincos(0.5 * wh, &rs, &rc);
+        const int64_t anchor = n0 - n0 % kAnchor;
+        set(anchor);
+        for (int64_t q = anchor; q < n0; ++q) {
+            half();
+            half();
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // device memory pool with an HBM budget (pool.cpp)
 // ---------------------------------------------------------------------------
@@ -302,6 +332,11 @@ struct DenseMfmaLaunch {
     const void *B1, *B2;       // FP16 operator fragments (hi, scaled lo)
     float inv_beta;            // 1 / beta, a power of two
     double h;
+    // damped, driven launches (method kMfmaDriven + EX): Rayleigh damping
+    // alpha M + beta K and the force M^-1 F cos(Omega t)
+    double alpha, beta;
+    const double *f;           // [batch][s] M^-1 F, or nullptr
+    const double *omega;       // [batch]
     const float *x0, *v0;
     float *state;
     float *sigma;              // [batch] per-instance scale, carried with the state
@@ -319,6 +354,9 @@ osc_status dense_mfma_launch_items(const DenseMfmaItem *items, int64_t nitems, i
 int dense_mfma_pad(int s);                       // padded size (multiple of 64), 0 if s > 256
 size_t dense_mfma_fragment_elems(int s);         // FP16 elements per operator part
 osc_status dense_mfma_fragments(int s, const double *A, double scale, _Float16 *B1, _Float16 *B2, hipStream_t st);
+// method: OSC_RK4, OSC_VERLET, or kMfmaDriven + EX (RK4 of a damped, driven
+// system; EX bit 0: beta != 0, bit 1: a force)
+constexpr int kMfmaDriven = 4;
 osc_status dense_mfma_launch(const DenseMfmaLaunch &a, int method, hipStream_t st);
 
 // ---------------------------------------------------------------------------

@@ -239,3 +239,48 @@ def test_driven_chain_register_and_workgroup_kernels_agree(prec, s):
     for got in out:
         ex, ev = _errs(got, ref)
         assert ex < TOL[prec] and ev < TOL[prec], (s, ex, ev)
+
+
+@pytest.mark.parametrize("s,batch", [(37, 19), (256, 17)])
+@pytest.mark.parametrize("terms", ["alpha", "beta", "force", "all"])
+def test_driven_dense_matrix_cores_and_workgroup_kernel_agree(s, batch, terms):
+    """A shared dense operator in FP32 runs damped, driven RK4 on the matrix
+    cores (the four-level recursion, one kernel per combination of terms);
+    OSC_CFG_DENSE_KERNEL = 1 takes the stage-form workgroup kernel instead.
+    Both match the oracle within the FP32 tolerance, over ragged 16-instance
+    tiles."""
+    w, alpha, beta, F, W = _dense_case(960 + s, batch, s, 1500, 300)
+    if terms == "alpha":
+        beta, F, W = 0.0, None, None
+    elif terms == "beta":
+        alpha, F, W = 0.0, None, None
+    elif terms == "force":
+        alpha = beta = 0.0
+    out = []
+    for kern in (0, 1):
+        sysm = osc.System("dense", "rk4", "f32", w.M, w.K, w.dt, shared=True, batch=batch).create()
+        try:
+            sysm.set_config(osc.CFG_DENSE_KERNEL, kern)
+            out.append(_run(sysm, w, "f32", alpha, beta, F, W))
+        finally:
+            sysm.close()
+    x0, v0 = f32_inputs(w)
+    ref = oracle.dense_driven(w.M, w.K, w.dt, alpha, beta, F, W, x0, v0, w.nsteps, w.out_stride)
+    for kern, got in zip((0, 1), out):
+        ex, ev = _errs(got, ref)
+        print(f"driven dense s={s} {terms} kernel {kern}: x {ex:.2e} v {ev:.2e}")
+        assert ex < 1e-5 and ev < 1e-5, (kern, ex, ev)
+
+
+def test_driven_dense_matrix_cores_chunked_and_static_are_bitwise_identical():
+    w, alpha, beta, F, W = _dense_case(975, 20, 48, 1000, 125)
+    sysm = osc.System("dense", "rk4", "f32", w.M, w.K, w.dt, shared=True, batch=20).create()
+    try:
+        whole = _run(sysm, w, "f32", alpha, beta, F, W)
+        chunked = _run(sysm, w, "f32", alpha, beta, F, W, steps_per_launch=77)
+        static = _run(sysm, w, "f32", alpha, beta, F, W, steps_per_launch=77, static=True)
+    finally:
+        sysm.close()
+    for a, b, c in zip(whole, chunked, static):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, c)
