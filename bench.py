@@ -5,7 +5,7 @@ Default workload (c3): 4096 fixed-free spring chains of s = 1024 bodies
 (eq. (2) generalised), masses U[0.5, 2], springs LogU[1e2, 1e4],
 x0 ~ N(0, sigma = 0.1), v0 = 0, dt = 0.01/omega_max per chain, 10^5 classic
 RK4 steps with FP32 state (synthetic, seeded): the largest configuration
-that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c3d, c4, c4v, c5;
+that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c3d, c4, c4v, c4d, c5;
 and the propagator modes: c1p and c2p, the per-step step matrix; c2j and c4j, frames
 by powers of the step matrix).
 
@@ -111,6 +111,9 @@ WORKLOADS = {
     "c3d": dict(kind="chain", method="rk4", prec="f32", driven=True,
                 desc="fixed-free spring chain: 4096 instances, s=1024, 1e4 RK4 steps, FP32, Rayleigh damping "
                      "(alpha=0.05, beta=1e-5) and a harmonic force per chain"),
+    "c4d": dict(kind="dense", method="rk4", prec="f32", driven=True,
+                desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, FP32, Rayleigh damping "
+                     "(alpha=0.02, beta=1e-3) and a harmonic force per instance (FP16 split MFMA)"),
     "c5": dict(kind="serve", method="rk4", prec="f32",
                desc="served stream: chains and dense SPD systems, s LogU[2,2048], nsteps LogU[1e3,1e5], FP32"),
 }
@@ -135,6 +138,10 @@ def make_workload(name):
     if name.startswith("c3"):
         w = workloads.c3_spring_chain()
         w.out_stride = w.nsteps
+        return w
+    if name == "c4d":
+        w, ex = workloads.c4_driven_dense()
+        w.excitation = ex
         return w
     if name.startswith("c4"):
         return workloads.c4_dense_shared()
@@ -195,8 +202,12 @@ def cpu_baseline(w, kind, method, prec, idx):
     t0 = time.perf_counter()
     if getattr(w, "excitation", None) is not None:
         ex = w.excitation.subset(idx)
-        xf, vf, _, _ = oracle.chain_driven(sub.m, sub.k, sub.dt, ex.alpha, ex.beta, ex.F, ex.omega, x0, v0,
-                                           w.nsteps, w.out_stride)
+        if kind == "chain":
+            xf, vf, _, _ = oracle.chain_driven(sub.m, sub.k, sub.dt, ex.alpha, ex.beta, ex.F, ex.omega, x0, v0,
+                                               w.nsteps, w.out_stride)
+        else:
+            xf, vf, _, _ = oracle.dense_driven(sub.M, sub.K, sub.dt, ex.alpha, ex.beta, ex.F, ex.omega, x0, v0,
+                                               w.nsteps, w.out_stride, shared=sub.shared)
     elif kind == "chain":
         xf, vf, _, _ = oracle.chain(method, sub.m, sub.k, sub.dt, x0, v0, w.nsteps, w.out_stride)
     else:
@@ -307,6 +318,18 @@ def bench_batched(args, name, spec):
     kavg = float(np.mean(kern_ms)) * 1e-3
     if mode == 1:
         roofline = jump_roofline(w, kind, kavg)
+    elif spec.get("driven") and kind == "dense":
+        # stage form: four stages of B X and B W; issued: the recursion's FP16
+        # passes (B x 3, B w 3 with stiffness damping, three level products)
+        fpd = 8 * 2 * w.s
+        passes = 3 + (3 if w.excitation.beta else 2) + 2 + (1 if w.excitation.beta else 0)
+        achieved = fpd * dof_steps / kavg / 1e12
+        hw = passes * 2 * w.s * dof_steps / kavg / 1e12
+        peak = PEAK["fp16_mfma"]
+        roofline = dict(bound="mfma", achieved=round(achieved, 2), peak=peak, unit="TFLOP/s",
+                        frac=round(achieved / peak, 4), traffic=measured_traffic(name),
+                        kernel="dense_mfma_kernel (damped, driven)", kernel_ms=round(kavg * 1e3, 4),
+                        flops_per_dof_step=fpd, hw_mfma_tflops=round(hw, 1), hw_mfma_frac=round(hw / peak, 4))
     elif spec.get("driven"):
         fpd = ALG_DRIVEN_CHAIN_FLOPS
         achieved = fpd * dof_steps / kavg / 1e12

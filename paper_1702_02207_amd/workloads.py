@@ -213,6 +213,18 @@ def c3_driven_chain(batch: int = 4096, s: int = 1024, nsteps: int = 10_000, out_
     return w, Excitation(0.05, 1e-5, F.copy(), omega.copy())
 
 
+def c4_driven_dense(batch: int = 8192, s: int = 256, nsteps: int = 10_000, out_stride: int = 1000):
+    """The C4 dense system (one operator shared by every instance, same x0)
+    with Rayleigh damping alpha = 0.02, beta = 1e-3, forces F ~ N(0, 1) per
+    DOF and one frequency omega ~ U[0.2, 2] per instance (the system's modes
+    span about 0.25 to 1.7 rad per unit time).  Returns (DenseBatch, Excitation)."""
+    w = c4_dense_shared(batch=batch, s=s, nsteps=nsteps, out_stride=out_stride)
+    rng = _rng(3, salt=1)
+    F = rng.normal(0.0, 1.0, (8192, s))[:batch]
+    omega = rng.uniform(0.2, 2.0, 8192)[:batch]
+    return w, Excitation(0.02, 1e-3, F.copy(), omega.copy())
+
+
 def haar_orthogonal(rng, s: int) -> np.ndarray:
     g = rng.normal(0.0, 1.0, (s, s))
     q, r = np.linalg.qr(g)
