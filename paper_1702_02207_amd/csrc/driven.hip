@@ -5,22 +5,34 @@
 // t_n, t_n + h/2, t_n + h/2, t_n + h).  In scaled time tau = t/h, w = h v,
 // B = h^2 A, f = M^-1 F the stage slope of w is
 //     kw = -B X - (alpha h) W - (beta / h) B W + h^2 f cos(Omega t).
-// One 256-thread workgroup per instance; thread t owns DOFs t, t + 256, ...
-// in registers.  Each stage writes its arguments (X, W) to LDS, in two
-// buffers used in turn, so that one barrier per stage separates the writes
-// from the reads of the products (the buffer written by a stage was last read
-// two stages earlier, before the barrier in between).  Chains take the
-// three-point stencil from LDS; dense systems stream the column-major operator.
+// The system is linear with constant coefficients (only the force depends on
+// t), so the four stages sum to a four-level recursion: with y = (x, w),
+// L y = (w, -B x - a w - b B w) (a = alpha h, b = beta / h), e = (0, h^2 f)
+// and the force phases c0, ch, ch, c1 of the stages,
+//     y_{n+1} = y + z1 + z2/2 + z3/6 + z4/24,   z1 = L y + g1 e,
+//     z_k = L z_{k-1} + g_k e,  g1 = c0, g2 = 2 (ch - c0), g3 = 0,
+//     g4 = 4 (c0 - 2 ch + c1)
+// (expand k1..k4 and match the coefficients of L^j e).  The x-part of z_k is
+// the w-part of z_{k-1}, so B of it is already known: a step takes B x (split
+// coefficients in FP32: the dominant term), B w and B of three w-parts (the
+// last only with stiffness damping) -- five products against the stage
+// form's eight.  The g_k are formed in FP64 from the FP64 phase.
 //
-// FP32: x and w are kept as hi + lo (Kahan update every step); B X uses the
-// operator split into high and low parts, B W the high part (it enters
-// smaller by h omega).  The stage arguments are X_s = x + c_s kx, W_s = w +
-// c_s kw, and the increments are summed with the dominant term last:
-//     dx = w + (kw1 + kw2 + kw3) / 6,   dw = (kw1 + kw4 + 2 (kw2 + kw3)) / 6.
-// The force's phase is a rotation in FP64, set exactly (sincos of Omega h n)
-// at every global step index divisible by 64 and advanced by half-step
-// rotations in between, so that chunked and unchunked runs agree bitwise.
-// Chains of s <= 1024 take a register-resident kernel instead (below).
+// Two kernels run this step.  One 256-thread workgroup per instance (dense
+// systems and chains of up to 2048 DOFs): thread t owns DOFs t, t + 256, ...
+// in registers; each level publishes its operand to LDS, in two buffers used
+// in turn, so that one barrier per level separates the writes from the reads
+// of the products (the buffer written by a level was last read two levels
+// earlier, before the barrier in between); chains take the three-point
+// stencil from LDS, dense systems stream the column-major operator.  Chains
+// of s <= 1024 take a register-resident kernel instead (below).  Shared dense
+// operators in FP32 run on the matrix cores (dense_mfma.hip).
+//
+// FP32: x and w are kept as hi + lo (Kahan update every step); the low parts
+// or per-DOF sums collect the z terms, the dominant term added last.  The
+// force's phase is the FP64 rotation of osc_internal.h (Phase), set exactly
+// at every global step index divisible by 64, so chunked and unchunked runs
+// agree bitwise.
 
 #include <cmath>
 #include <type_traits>
@@ -137,35 +149,25 @@ __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
         }
     };
 
-    int cur = 0;   // LDS buffer of the next stage
+    int cur = 0;   // LDS buffer of the next publication
     const bool single = a.nbuf == 1;
-    // one stage: publish (X, W), then kw = F(X, W) at the given force value
-    auto stage = [&](const T (&X)[RPT], const T (&W)[RPT], T force, T (&kw)[RPT]) {
+    // publish U (and V into the buffer's second half when given) for the
+    // products of the next level
+    auto publish = [&](const T (&U)[RPT], const T *V) {
         T *ux = buf[cur], *uw = buf[cur] + pitch;
-        if (single) __syncthreads();   // one buffer: every read of the previous stage is done
+        if (single) __syncthreads();   // one buffer: every read of the previous level is done
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int i = tid + r * kThreads;
             if (i < s) {
-                ux[i + 1] = X[r];
-                uw[i + 1] = W[r];
+                ux[i + 1] = U[r];
+                if (V) uw[i + 1] = V[r];
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int i = tid + r * kThreads;
-            if (i >= s) {
-                kw[r] = T(0);
-                continue;
-            }
-            T acc = -bop(ux, r, true);
-            if (use_beta) acc = fma_t(-dampb, bop(uw, r, false), acc);
-            acc = fma_t(-dampw, W[r], acc);
-            if (forced) acc = fma_t(fh[r], force, acc);
-            kw[r] = acc;
-        }
+        T *out = buf[cur];
         if (!single) cur ^= 1;
+        return out;
     };
 
     const bool untouched = a.load_mode == LOAD_USER;
@@ -174,41 +176,77 @@ __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
     const int64_t nend = a.n0 + a.nsteps;
     if (stride > 0 && untouched && n % stride == 0) write_frame(n / stride, true);
     while (n < nend) {
-        if (forced && n % kAnchor == 0) ph.set(n);
-        const T f0 = (T)ph.c;
-        if (forced) ph.half();
-        const T fhalf = (T)ph.c;
-        if (forced) ph.half();
-        const T f1 = (T)ph.c;
-        T xe[RPT], we[RPT], X[RPT], W[RPT], k1[RPT], k2[RPT], k3[RPT], k4[RPT];
+        // the RK4 map as the four-level recursion of the register kernel
+        // below: z1 = L y + g1 e, z_k = L z_{k-1} + g_k e, y += z1 + z2/2 +
+        // z3/6 + z4/24, the x-part of each level the w-part of the one before
+        T g1 = T(0), g2 = T(0), g4 = T(0);
+        if (forced) {
+            if (n % kAnchor == 0) ph.set(n);
+            const double c0 = ph.c;
+            ph.half();
+            const double ch = ph.c;
+            ph.half();
+            const double c1 = ph.c;
+            g1 = (T)c0;
+            g2 = (T)(2.0 * (ch - c0));
+            g4 = (T)(4.0 * ((c0 - ch) + (c1 - ch)));
+        }
+        T xe[RPT], we[RPT], Bp[RPT], V[RPT], R[RPT], sx[RPT], sw[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             xe[r] = COMP ? x[r] + xl[r] : x[r];
             we[r] = COMP ? w[r] + wl[r] : w[r];
         }
-        stage(xe, we, f0, k1);
+        const T *u = publish(xe, we);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            X[r] = fma_t(T(0.5), we[r], xe[r]);
-            W[r] = fma_t(T(0.5), k1[r], we[r]);
+            const bool own = tid + r * kThreads < s;
+            R[r] = own ? bop(u, r, true) : T(0);               // B x
+            Bp[r] = own ? bop(u + pitch, r, false) : T(0);     // B w = B z1_x
+            T v = fma_t(-dampw, we[r], -R[r]);
+            if (use_beta) v = fma_t(-dampb, Bp[r], v);
+            if (forced) v = fma_t(fh[r], g1, v);
+            V[r] = own ? v : T(0);   // z1_w
+            sx[r] = T(0.5) * V[r];
+            sw[r] = V[r];
         }
-        stage(X, W, fhalf, k2);
+        u = publish(V, nullptr);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            X[r] = fma_t(T(0.5), W[r], xe[r]);
-            W[r] = fma_t(T(0.5), k2[r], we[r]);
+            const bool own = tid + r * kThreads < s;
+            R[r] = own ? bop(u, r, false) : T(0);   // B z1_w = B z2_x
+            T v = fma_t(-dampw, V[r], -Bp[r]);
+            if (use_beta) v = fma_t(-dampb, R[r], v);
+            if (forced) v = fma_t(fh[r], g2, v);
+            V[r] = own ? v : T(0);   // z2_w
+            Bp[r] = R[r];
+            sx[r] = fma_t(T(1.0 / 6.0), V[r], sx[r]);
+            sw[r] = fma_t(T(0.5), V[r], sw[r]);
         }
-        stage(X, W, fhalf, k3);
+        u = publish(V, nullptr);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            X[r] = xe[r] + W[r];
-            W[r] = we[r] + k3[r];
+            const bool own = tid + r * kThreads < s;
+            R[r] = own ? bop(u, r, false) : T(0);   // B z2_w = B z3_x
+            T v = fma_t(-dampw, V[r], -Bp[r]);
+            if (use_beta) v = fma_t(-dampb, R[r], v);
+            V[r] = own ? v : T(0);   // z3_w
+            Bp[r] = R[r];
+            sx[r] = fma_t(T(1.0 / 24.0), V[r], sx[r]);
+            sw[r] = fma_t(T(1.0 / 6.0), V[r], sw[r]);
         }
-        stage(X, W, f1, k4);
+        if (use_beta) {
+            u = publish(V, nullptr);
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) R[r] = tid + r * kThreads < s ? bop(u, r, false) : T(0);   // B z3_w
+        }
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const T dx = fma_t(T(1.0 / 6.0), k1[r] + k2[r] + k3[r], we[r]);
-            const T dw = (k1[r] + k4[r] + T(2) * (k2[r] + k3[r])) * T(1.0 / 6.0);
+            T v = fma_t(-dampw, V[r], -Bp[r]);
+            if (use_beta) v = fma_t(-dampb, R[r], v);
+            if (forced) v = fma_t(fh[r], g4, v);   // z4_w
+            const T dx = we[r] + sx[r];
+            const T dw = fma_t(T(1.0 / 24.0), v, sw[r]);
             comp_add(x[r], xl[r], dx);
             comp_add(w[r], wl[r], dw);
         }
@@ -243,26 +281,12 @@ __global__ void __launch_bounds__(kThreads) driven_kernel(DrivenLaunch<T> a) {
 // per instance (LPI = 64, DPL consecutive DOFs per lane, s <= 64 DPL).  The
 // stencil's neighbouring values across lanes come from whole-wave DPP shifts
 // (zero outside the wave: the wall, and beyond the free end, whose
-// coefficient is zero); no LDS, no barrier.
-//
-// The step is the same RK4 map as the stage form above, in the form a linear
-// system with constant coefficients allows.  With y = (x, w), the operator
-// L y = (w, -B x - a w - b B w) (a = alpha h, b = beta / h) and the force
-// direction e = (0, h^2 f), the four stages with force phases c0, ch, ch, c1
-// (at t_n, t_n + h/2, t_n + h) sum to
-//     y_{n+1} = y + z1 + z2/2 + z3/6 + z4/24,   z1 = L y + g1 e,
-//     z_k = L z_{k-1} + g_k e,  g1 = c0, g2 = 2 (ch - c0), g3 = 0,
-//     g4 = 4 (c0 - 2 ch + c1)
-// (expand k1..k4 and match the coefficients of L^j e).  The x-part of z_k is
-// the w-part of z_{k-1}, so B of it is already known: one step takes B x
-// (split coefficients: it is the dominant term), B w, B z1_w, B z2_w and,
-// with stiffness damping, B z3_w -- five stencils against the stage form's
-// eight, four of them with the high coefficients only.  The g_k are formed
-// in FP64 from the FP64 phase before rounding to T.  The low parts of x and
-// w collect the z terms as they are formed and one Kahan step per variable
-// ends the step (FP64: a plain update), so chunked, static and real-time
-// runs agree bitwise as for the stage form.  Two waves per SIMD except for
-// FP64 with 16 DOFs per lane (one).
+// coefficient is zero); no LDS, no barrier.  The step is the recursion above:
+// B x with split coefficients, B w, B z1_w, B z2_w and, with stiffness
+// damping, B z3_w, four of the five stencils with the high coefficients only.
+// The low parts of x and w collect the z terms as they are formed and one
+// Kahan step per variable ends the step (FP64: a plain update).  Two waves
+// per SIMD except for FP64 with 16 DOFs per lane (one).
 // EX: bit 0 Rayleigh beta != 0 (the stiffness-proportional damping term),
 // bit 1 a force; fixed per launch, so that each step is one basic block.
 template <typename T, int DPL, int LPI, int EX>
