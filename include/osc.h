@@ -358,10 +358,10 @@ osc_status osc_rt_run(osc_rt *rt, double period_s, int64_t nticks, void *x_frame
 
 /*
  * osc_rt_run_resident -- the same periodic loop with one kernel resident on
- * the device for the whole run instead of one launch per tick (chain handles
- * only, not damped or driven, not in a propagator mode: OSC_ENOTSUP
- * otherwise, also when the batch needs more workgroups than the device holds
- * at once).  At each release the host raises a counter in host-mapped memory;
+ * the device for the whole run instead of one launch per tick (chain handles,
+ * damped or driven ones with s <= 1024 on the register kernels, not in a
+ * propagator mode: OSC_ENOTSUP otherwise, also when the batch needs more
+ * workgroups than the device holds at once).  At each release the host raises a counter in host-mapped memory;
  * every workgroup of the kernel polls it, advances its instances one tick,
  * stores the tick's result (x_frames / v_frames as for osc_rt_run, else the
  * stepper's own output buffers) and raises a completion count the host polls.

@@ -1039,21 +1039,15 @@ osc_status sys_rt_supported(const osc_sys *s) {
 
 osc_status sys_rt_resident_supported(const osc_sys *s) {
     if (s->kind != OSC_CHAIN) return fail(OSC_ENOTSUP, "resident real-time stepping takes chains only");
-    if (s->driven) return fail(OSC_ENOTSUP, "resident real-time stepping: damped or driven chains are not supported");
+    if (s->driven && (s->s > 1024 || s->dense_kernel == 1))
+        return fail(OSC_ENOTSUP, "resident real-time stepping of damped or driven chains takes the register "
+                                 "kernels (s <= 1024)");
     if (s->propagator != 0) return fail(OSC_ENOTSUP, "resident real-time stepping takes the stepping integrators");
     return OSC_OK;
 }
 
 template <typename T>
 osc_status rt_resident(osc_sys *s, const void *x0, const void *v0, const ResidentSpec &spec, int64_t *blocks) {
-    ChainLaunch<T> a{};
-    a.batch = s->batch;
-    a.s = s->s;
-    a.c = coef_of<T>(s);
-    a.x0 = static_cast<const T *>(x0);
-    a.v0 = static_cast<const T *>(v0);
-    a.state = static_cast<T *>(state_buf(s));
-    a.nonfinite = s->flag;
     ResidentRun<T> r{};
     r.ctl = spec.ctl;
     r.first_release = 0;
@@ -1065,6 +1059,32 @@ osc_status rt_resident(osc_sys *s, const void *x0, const void *v0, const Residen
     r.vf = static_cast<T *>(spec.vf);
     r.xo = static_cast<T *>(spec.xo);
     r.vo = static_cast<T *>(spec.vo);
+    if (s->driven) {
+        DrivenLaunch<T> d{};
+        d.kind = OSC_CHAIN;
+        d.batch = s->batch;
+        d.s = s->s;
+        d.c = coef_of<T>(s);
+        d.h = s->h;
+        d.alpha = s->alpha;
+        d.beta = s->beta;
+        d.f = s->force;
+        d.omega = s->omega;
+        d.x0 = static_cast<const T *>(x0);
+        d.v0 = static_cast<const T *>(v0);
+        d.state = static_cast<T *>(state_buf(s));
+        d.nonfinite = s->flag;
+        *blocks = driven_resident_blocks<T>(d);
+        return driven_resident_launch<T>(d, r, s->stream);
+    }
+    ChainLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.c = coef_of<T>(s);
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.state = static_cast<T *>(state_buf(s));
+    a.nonfinite = s->flag;
     *blocks = chain_resident_blocks<T>(a, s->cfg);
     return chain_resident_launch<T>(a, s->method, s->cfg, r, s->stream);
 }

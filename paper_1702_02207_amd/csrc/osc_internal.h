@@ -211,6 +211,13 @@ osc_status chain_resident_launch(const ChainLaunch<T> &a, int method, ChainConfi
                                  hipStream_t st);
 template <typename T>
 int64_t chain_resident_blocks(const ChainLaunch<T> &a, ChainConfig cfg);
+// the same for damped, driven chains of s <= 1024 (register layouts)
+template <typename T>
+struct DrivenLaunch;
+template <typename T>
+osc_status driven_resident_launch(const DrivenLaunch<T> &a, const ResidentRun<T> &r, hipStream_t st);
+template <typename T>
+int64_t driven_resident_blocks(const DrivenLaunch<T> &a);
 
 // ---------------------------------------------------------------------------
 // coefficient preparation, stability bound and energy (prep.hip)

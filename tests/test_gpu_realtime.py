@@ -144,19 +144,23 @@ def test_realtime_rejects_unsupported_paths():
         sysm.close()
 
 
-@pytest.mark.parametrize("case", ["chain_f32", "chain_verlet", "chain_long", "chain_f64", "two_wave_chain"])
+@pytest.mark.parametrize("case", ["chain_f32", "chain_verlet", "chain_long", "chain_f64", "two_wave_chain",
+                                  "driven", "driven_long_f64"])
 def test_resident_ticks_are_the_frames_of_one_integration(case):
     """osc_rt_run_resident: one kernel stays on the device and advances one
     tick per release; its frames are bit for bit those of osc_integrate, also
     when launch-mode ticks come before and after it."""
     import torch
     k, n_before, n_res, n_after = 5, 3, 30, 2
-    s = {"chain_long": 1024, "two_wave_chain": 1500}.get(case, 8)
+    s = {"chain_long": 1024, "two_wave_chain": 1500, "driven_long_f64": 1000}.get(case, 8)
     m, kk, dt, x0, v0 = _chain(2000 + len(case), 6, s)
     method = "verlet" if case == "chain_verlet" else "rk4"
-    prec = "f64" if case == "chain_f64" else "f32"
+    prec = "f64" if case in ("chain_f64", "driven_long_f64") else "f32"
     dtype = torch.float64 if prec == "f64" else torch.float32
     sysm = osc.System("chain", method, prec, m, kk, dt).create()
+    if case.startswith("driven"):
+        rng = np.random.default_rng(2003)
+        sysm.set_excitation(0.2, 1e-4, rng.normal(size=(6, s)) * 10.0, rng.uniform(5, 20, 6))
     X0, V0 = to_dev(x0, dtype), to_dev(v0, dtype)
     try:
         total = n_before + n_res + n_after
@@ -218,11 +222,13 @@ def test_resident_rejects_unsupported_handles():
             assert e.value.status == osc.OSC_ENOTSUP
     finally:
         sysm.close()
+    # damped chains on the one-workgroup-per-instance kernel
     m, k, dt, x0, v0 = _chain(2011, 4, 8)
     sysm = osc.System("chain", "rk4", "f32", m, k, dt).create()
     X0 = to_dev(x0, torch.float32)
     try:
         sysm.set_excitation(0.1, 0.0, None)
+        sysm.set_config(osc.CFG_DENSE_KERNEL, 1)
         with osc.Realtime(sysm, X0, X0, 1) as rt:
             with pytest.raises(osc.OscError) as e:
                 rt.run_resident(1e-3, 2)
