@@ -218,8 +218,10 @@ osc_status osc_set_excitation(osc_sys *sys, double alpha, double beta, const dou
  * P_k = P_1^k by repeated squaring, all in FP64 on the GPU.
  * P: device double [nsys][2s][2s] row-major, positions first (nsys = batch
  * for chains and per-instance dense systems, 1 for a shared operator).
- * s <= 256 (OSC_ENOTSUP otherwise).  k = 0 gives the identity.  Ordered on
- * the handle's stream; for s > 2 the call waits for its own temporaries.
+ * Any s up to 2048; for s > 2 the call takes device temporaries of four
+ * [nsys][2s][2s] FP64 matrices (OSC_ENOMEM when they do not fit).  k = 0
+ * gives the identity.  Ordered on the handle's stream; for s > 2 the call
+ * waits for its own temporaries.
  */
 osc_status osc_propagator(osc_sys *sys, int64_t k, double *P);
 
@@ -259,7 +261,9 @@ osc_status osc_dense_operator(osc_sys *sys, double *A);
  *                             frame by one product with it, the rest of the run
  *                             by P^r (r = nsteps - last frame step; P^nsteps
  *                             when out_stride == 0), with the state in FP64
- *                             (s <= 256): the scheme's own trajectory at the
+ *                             (any s; for s > 2 six [nsys][2s][2s] FP64
+ *                             temporaries, OSC_ENOMEM from osc_integrate when
+ *                             they do not fit): the scheme's own trajectory at the
  *                             frames, rounded differently and not computed at
  *                             the steps in between; 2 per-step propagator for
  *                             chains of s <= 2: each step applies P - I (FP32:

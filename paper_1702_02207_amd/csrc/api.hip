@@ -797,7 +797,6 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
             return OSC_OK;
         case OSC_CFG_PROPAGATOR:
             if (value < 0 || value > 2) return fail(OSC_EINVAL, "propagator mode must be 0, 1 or 2");
-            if (value == 1 && s->s > 256) return fail(OSC_ENOTSUP, "frame jumps take s <= 256");
             if (value == 2 && !(s->kind == OSC_CHAIN && s->s <= 2))
                 return fail(OSC_ENOTSUP, "the per-step propagator takes chains of s <= 2");
             s->propagator = (int)value;
@@ -989,7 +988,6 @@ osc_status osc_propagator(osc_sys *s, int64_t k, double *P) {
     g_last_error.clear();
     if (!s || !P) return fail(OSC_EINVAL, "handle and P must be non-NULL");
     if (k < 0) return fail(OSC_EINVAL, "k must be >= 0");
-    if (s->s > 256) return fail(OSC_ENOTSUP, "osc_propagator takes s <= 256");
     if (s->batch == 0) return OSC_OK;
     return propagator_matrix(prop_args(s), s->s, k, P, s->stream);
 }

@@ -16,7 +16,7 @@
 //     step applies P - I, split into FP32 high and low parts, to the
 //     compensated state, one lane per instance.
 // Systems of s <= 2 keep P in registers, one lane per system; larger ones
-// (s <= 256) form P^k and apply it by FP64 matrix-core products: the
+// (up to s = 2048) form P^k and apply it by FP64 matrix-core products: the
 // squarings and the frame jumps are plain GEMMs (row-major n x n by n x n,
 // and batch x n by the transposed n x n), which run through rocBLAS's DGEMM.
 

@@ -72,7 +72,7 @@ def test_chain_propagator_matches_oracle(method, s, batch, k):
 
 
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
-@pytest.mark.parametrize("s,k", [(2, 1), (2, 1000), (5, 37), (64, 1), (64, 1000), (130, 7)])
+@pytest.mark.parametrize("s,k", [(2, 1), (2, 1000), (5, 37), (64, 1), (64, 1000), (130, 7), (300, 5)])
 def test_dense_propagator_matches_oracle(method, s, k):
     w = _dense(720 + s, 2, s, 1, 0)
     sysm = osc.System("dense", method, "f64", w.M, w.K, w.dt, shared=True, batch=2).create()
@@ -139,7 +139,7 @@ def _check_traj(got, ref, tol, label):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
 @pytest.mark.parametrize("s,batch,nsteps,stride", [(1, 37, 2000, 250), (2, 300, 3000, 700), (2, 5, 1234, 0),
-                                                   (3, 9, 800, 100), (7, 4, 600, 250)])
+                                                   (3, 9, 800, 100), (7, 4, 600, 250), (300, 2, 800, 100)])
 def test_chain_frame_jumps(method, prec, s, batch, nsteps, stride):
     """Frames by powers of the one-step matrix (registers for s <= 2, batched
     matrix-core products beyond): the scheme's trajectory at the frames;
@@ -156,7 +156,8 @@ def test_chain_frame_jumps(method, prec, s, batch, nsteps, stride):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 @pytest.mark.parametrize("method", ["rk4", "verlet"])
-@pytest.mark.parametrize("s,batch,shared", [(2, 50, True), (5, 3, False), (64, 70, True), (100, 20, True)])
+@pytest.mark.parametrize("s,batch,shared", [(2, 50, True), (5, 3, False), (64, 70, True), (100, 20, True),
+                                            (300, 2, True)])
 def test_dense_frame_jumps(method, prec, s, batch, shared):
     w = _dense(780 + s, batch, s, 2000, 300, shared=shared)
     sysm = osc.System("dense", method, prec, w.M, w.K, w.dt, shared=shared, batch=batch).create()
@@ -166,6 +167,29 @@ def test_dense_frame_jumps(method, prec, s, batch, shared):
         sysm.close()
     _check_traj(got, _oracle_for(w, method, prec), 1e-6 if prec == "f32" else TOL_F64,
                 f"dense jumps {method} {prec} s={s}")
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_dense_frame_jumps_at_the_largest_size(method):
+    """s = 2048, the largest size the library takes: frames by powers of the
+    4096 x 4096 one-step matrix, against the exact discrete solution of the
+    scheme per normal mode (LAPACK eigh of (K, M); the FP64 oracle's own
+    stepping needs minutes at this size).  An FP64 replica of the jumps on
+    the CPU meets that closed form to 2e-13."""
+    w = _dense(2801, 1, 2048, 1000, 250)
+    sysm = osc.System("dense", method, "f64", w.M, w.K, w.dt, shared=True, batch=1).create()
+    try:
+        xf, vf, xe, ve = _gpu_run(sysm, w, "f64", 1)
+    finally:
+        sysm.close()
+    exact = cf.rk4_discrete if method == "rk4" else cf.verlet_discrete
+    rx, rv = exact(np.arange(0, 1001, 250), w.dt[0], w.M, w.K, w.x0[0], w.v0[0])
+    ex = oracle.rel_traj_err(xf, rx[:, None, :]).max()
+    ev = oracle.rel_traj_err(vf, rv[:, None, :]).max()
+    print(f"s=2048 {method} jumps against the modal solution: x {ex:.2e} v {ev:.2e}")
+    assert max(ex, ev) < TOL_F64
+    np.testing.assert_array_equal(xf[-1], xe)
+    np.testing.assert_array_equal(vf[-1], ve)
 
 
 def test_paper_system_frame_jumps_match_closed_form():
