@@ -431,6 +431,8 @@ def serve_pass(args, method="rk4", prec="f32"):
     _log(f"[bench] serving: Poisson arrivals at {qps:.2f} requests/s")
     arr = serve.poisson_arrivals(len(reqs), qps, seed=1702022074)
     run = serve.run_stream(reqs, arr, method=method, prec=prec, hbm_budget=args.hbm_budget)
+    _log("[bench] serving: the same arrivals, dense frames by jumps where much cheaper")
+    jr = serve.run_stream(reqs, arr, method=method, prec=prec, hbm_budget=args.hbm_budget, frame_jumps=True)
 
     # slowdown against the request served alone, on a seeded sample that
     # always holds the largest request of each kind
@@ -471,6 +473,14 @@ def serve_pass(args, method="rk4", prec="f32"):
         "slowdown_vs_alone": slowdown(run), "alone_sample": len(sample),
         "hbm_peak_bytes": run["hbm_peak_bytes"], "iterations": run["iterations"],
         "worker_setup_s": run["worker_setup_s"], "worker_iterate_s": run["worker_iterate_s"],
+        "frame_jumps": {
+            "note": "same stream and arrivals; dense requests whose frames cost much less by powers of the "
+                    "one-step matrix (FP64) are served that way: their steps are represented, not computed",
+            "requests_by_jumps": len(jr["by_frame_jumps"]),
+            "dof_steps_by_jumps": int(sum(reqs[i].system.s * reqs[i].system.nsteps for i in jr["by_frame_jumps"])),
+            "p50_latency_s": jr["p50_latency_s"], "p99_latency_s": jr["p99_latency_s"],
+            "mean_latency_s": jr["mean_latency_s"], "makespan_s": jr["makespan_s"], "per_kind": per_kind(jr),
+            "failed": jr["failed"], "worker_setup_s": jr["worker_setup_s"]},
         "saturation": {"requests_per_s": sat_qps, "dof_steps_per_s": sat["dof_steps_per_s"],
                        "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"],
                        "per_kind": per_kind(sat), "slowdown_vs_alone": slowdown(sat)},

@@ -411,6 +411,10 @@ typedef struct osc_server_config {
     int32_t max_slots;        /* requests admitted at once (>= 1) */
     int32_t chunk_us;         /* target GPU time of one request chunk, microseconds (0 = 2000) */
     int32_t fake_executor;    /* 1: no device work; chunks take simulated time (scheduler tests) */
+    int32_t frame_jumps;      /* 1: a dense request whose frames cost much less to reach by powers
+                                 of its one-step matrix (OSC_CFG_PROPAGATOR = 1, FP64) than by
+                                 stepping is served that way, whole, by the admitting thread;
+                                 0: every request is stepped */
 } osc_server_config;
 
 typedef struct osc_request_info {
@@ -419,6 +423,7 @@ typedef struct osc_request_info {
     double latency_s;         /* submit -> results ready */
     int64_t bytes;            /* device bytes accounted to the request */
     int64_t iterations;       /* scheduler iterations the request took part in */
+    int32_t frame_jumps;      /* 1 if the request was served by frame jumps */
 } osc_request_info;
 
 typedef struct osc_server_counters {

@@ -18,7 +18,8 @@
 // Systems of s <= 2 keep P in registers, one lane per system; larger ones
 // (up to s = 2048) form P^k and apply it by FP64 matrix-core products: the
 // squarings and the frame jumps are plain GEMMs (row-major n x n by n x n,
-// and batch x n by the transposed n x n), which run through rocBLAS's DGEMM.
+// and batch x n by the transposed n x n), which run through rocBLAS's DGEMM
+// with atomics off, so that a result does not depend on the run.
 
 #include <algorithm>
 #include <map>
@@ -330,9 +331,14 @@ osc_status dgemm(hipStream_t st, bool trans_a, int m, int n, int k, const double
     OSC_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(blas_mutex);
     rocblas_handle &h = blas_handles[dev];
-    if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
-        h = nullptr;
-        return fail(OSC_EDEVICE, "rocblas_create_handle failed");
+    if (!h) {
+        if (rocblas_create_handle(&h) != rocblas_status_success) {
+            h = nullptr;
+            return fail(OSC_EDEVICE, "rocblas_create_handle failed");
+        }
+        // no atomics: the same products give the same bits on every call
+        if (rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success)
+            return fail(OSC_EDEVICE, "rocblas_set_atomics_mode failed");
     }
     if (rocblas_set_stream(h, st) != rocblas_status_success) return fail(OSC_EDEVICE, "rocblas_set_stream failed");
     const double one = 1.0, zero = 0.0;

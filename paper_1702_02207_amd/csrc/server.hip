@@ -20,6 +20,10 @@
 // iteration; seconds per step come from a per-shape estimate that each
 // iteration updates from events around its launches (a fixed formula until a
 // shape has been seen).
+// With frame jumps enabled, a dense request whose frames cost much less to
+// reach by powers of its one-step matrix (the scheme's own trajectory at the
+// frames, formed and applied in FP64) than by stepping is served whole by
+// the setup thread and never joins an iteration.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -63,6 +67,7 @@ struct Req {
     osc_sys *sys = nullptr;
     void *dx0 = nullptr, *dv0 = nullptr, *dxf = nullptr, *dvf = nullptr, *dxe = nullptr, *dve = nullptr;
     bool split = false, mfma = false;
+    bool jump = false;           // served whole by frame jumps at admission
     int64_t done = 0, chunk = 0;
     // results
     std::vector<unsigned char> hxf, hvf, hxe, hve;
@@ -72,7 +77,7 @@ constexpr int kStreams = 4;
 
 // Conservative device bytes of a request: every allocation rounded to the
 // pool's size classes.
-int64_t estimate_bytes(const osc_desc &d, int64_t nframes) {
+int64_t estimate_bytes(const osc_desc &d, int64_t nframes, bool jump) {
     const size_t e = d.prec == OSC_F64 ? 8 : 4;
     const size_t s = (size_t)d.s;
     size_t b = 0;
@@ -95,8 +100,36 @@ int64_t estimate_bytes(const osc_desc &d, int64_t nframes) {
             add(fe); add(fe);
         }
         add(dense_split_scratch_elems((int)s, 1) * e + 64);      // split scratch
+        if (jump) {                                              // frame jumps: A^2, six 2s x 2s
+            add(ss * 8);                                         // matrices, two states (FP64)
+            for (int i = 0; i < 6; ++i) add(4 * ss * 8);
+            add(2 * s * 8); add(2 * s * 8);
+        }
     }
     return (int64_t)b;
+}
+
+// Whether a dense request's frames cost much less by frame jumps than by
+// stepping.  Jumps: FP64 products of 2s x 2s matrices (A^2, squarings and
+// multiplications for P^out_stride and the remainder power) at about 35
+// TFLOP/s, 20 us per frame, 1 ms of set-up.  Stepping: seconds per step of
+// the path the request would take (one instance: the split path beyond
+// s = 256, matrix cores for FP32 up to 256, else the vector kernel), as
+// measured for a lone instance.  Jumps are taken below half the stepping time.
+bool jumps_pay(const osc_desc &d, int64_t nsteps, int64_t out_stride) {
+    if (d.kind != OSC_DENSE || nsteps <= 0) return false;
+    const double s = d.s;
+    const int64_t nf = out_stride > 0 ? nsteps / out_stride + 1 : 0;
+    const int64_t k = std::max<int64_t>(1, out_stride > 0 ? out_stride : nsteps);
+    int bits = 0;
+    while ((k >> bits) > 0) ++bits;
+    const double gemm_s = 2.0 * (2 * s) * (2 * s) * (2 * s) / 35e12;
+    const double jump_s = (1 + 2 * bits + 2) * gemm_s + 20e-6 * (double)nf + 1e-3;
+    double step_s;
+    if (s > 256) step_s = 1.0e-5 + 1.8e-12 * s * s;
+    else if (d.prec == OSC_F32) step_s = 1e-6 + 8e-11 * s * s;
+    else step_s = 2e-6 + 1.2e-9 * s * s;
+    return jump_s < 0.5 * step_s * (double)nsteps;
 }
 
 // First guess of the seconds per step of one instance, before its shape's
@@ -193,7 +226,8 @@ struct Server {
 
     void loop();
     void setup_loop();
-    bool setup(Req *r);   // false: the request has been finished (failed) and may be gone
+    bool setup(Req *r);   // false: the request has been finished (failed, or served by jumps) and may be gone
+    bool serve_by_jumps(Req *r);
     void run_iteration(std::vector<Req *> &act);
     void finish(Req *r, osc_status st, const std::string &msg);
     void release_device(Req *r);
@@ -262,8 +296,8 @@ bool Server::setup(Req *r) {
     }
     r->split = r->desc.kind == OSC_DENSE && dense_uses_split(r->sys);
     r->mfma = r->desc.kind == OSC_DENSE && r->desc.prec == OSC_F32 && r->sys->F1 != nullptr;
-    st = sys_ensure_state(r->sys);
-    if (st == OSC_OK && r->split) st = sys_ensure_split_scratch(r->sys);
+    st = r->jump ? OSC_OK : sys_ensure_state(r->sys);
+    if (st == OSC_OK && r->split && !r->jump) st = sys_ensure_split_scratch(r->sys);
     if (st != OSC_OK || !r->dx0 || !r->dv0 || !r->dxe || !r->dve || (r->nframes > 0 && (!r->dxf || !r->dvf))) {
         finish(r, OSC_ENOMEM, "device memory exhausted while admitting a request");
         return false;
@@ -274,12 +308,43 @@ bool Server::setup(Req *r) {
         finish(r, OSC_EDEVICE, "upload of the initial state failed");
         return false;
     }
+    if (r->jump) return serve_by_jumps(r);
     r->chunk = chunk_of(*r);
     // the setup stream is drained; from here on the handle's own stream is
     // one the worker drains every iteration, so the completion path never
     // waits behind another request's setup
     r->sys->stream = streams[0];
     return true;
+}
+
+// A request served whole by frame jumps on the setup stream (powers of its
+// one-step matrix in FP64, one product per frame) and its results
+// downloaded; it is finished here and never joins an iteration.
+bool Server::serve_by_jumps(Req *r) {
+    const size_t s = (size_t)r->desc.s, bytes = s * r->elem;
+    osc_status st = osc_set_config(r->sys, OSC_CFG_PROPAGATOR, 1);
+    if (st == OSC_OK)
+        st = osc_integrate(r->sys, r->dx0, r->dv0, r->nsteps, r->out_stride, r->dxf, r->dvf, r->dxe, r->dve);
+    std::string msg = st == OSC_OK ? std::string() : std::string(osc_last_error());
+    if (st == OSC_OK) {
+        bool ok = hipMemcpyAsync(r->hxe.data(), r->dxe, bytes, hipMemcpyDeviceToHost, setup_stream) == hipSuccess &&
+                  hipMemcpyAsync(r->hve.data(), r->dve, bytes, hipMemcpyDeviceToHost, setup_stream) == hipSuccess;
+        if (r->nframes > 0)
+            ok = ok &&
+                 hipMemcpyAsync(r->hxf.data(), r->dxf, r->nframes * bytes, hipMemcpyDeviceToHost, setup_stream) ==
+                     hipSuccess &&
+                 hipMemcpyAsync(r->hvf.data(), r->dvf, r->nframes * bytes, hipMemcpyDeviceToHost, setup_stream) ==
+                     hipSuccess;
+        ok = ok && hipStreamSynchronize(setup_stream) == hipSuccess;
+        if (!ok) {
+            st = OSC_EDEVICE;
+            msg = "download of the results failed";
+        } else if ((st = osc_sync(r->sys)) != OSC_OK) {
+            msg = osc_last_error();
+        }
+    }
+    finish(r, st, msg);
+    return false;
 }
 
 // Build the work lists of one precision into wl (split-path requests, which
@@ -566,7 +631,7 @@ void Server::setup_loop() {
             ++in_setup;
         }
         const double t0 = now_s();
-        const bool ok = setup(r);   // a failed request is finished there; r must not be touched after
+        const bool ok = setup(r);   // a failed or jump-served request is finished there; r must not be touched after
         const double t1 = now_s();
         std::lock_guard<std::mutex> lk(mu);
         --in_setup;
@@ -680,7 +745,8 @@ osc_status osc_server_submit(osc_server *srv, const osc_desc *d, const void *x0,
     r->nsteps = nsteps;
     r->out_stride = out_stride;
     r->nframes = out_stride > 0 ? nsteps / out_stride + 1 : 0;
-    r->bytes = estimate_bytes(r->desc, r->nframes);
+    r->jump = S.cfg.frame_jumps != 0 && !S.cfg.fake_executor && jumps_pay(r->desc, nsteps, out_stride);
+    r->bytes = estimate_bytes(r->desc, r->nframes, r->jump);
     if (S.cfg.hbm_budget && (size_t)r->bytes > S.cfg.hbm_budget) {
         delete r;
         return fail(OSC_ENOMEM, "request needs more device memory than the whole budget");
@@ -718,6 +784,7 @@ osc_status osc_server_wait(osc_server *srv, uint64_t ticket, double timeout_s, v
         info->latency_s = r->t_done - r->t_submit;
         info->bytes = r->bytes;
         info->iterations = r->iterations;
+        info->frame_jumps = r->jump ? 1 : 0;
     }
     const osc_status st = r->status;
     if (st == OSC_OK) {

@@ -49,12 +49,12 @@ class Desc(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
-                ("chunk_us", ctypes.c_int32), ("fake_executor", ctypes.c_int32)]
+                ("chunk_us", ctypes.c_int32), ("fake_executor", ctypes.c_int32), ("frame_jumps", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double),
-                ("bytes", ctypes.c_int64), ("iterations", ctypes.c_int64)]
+                ("bytes", ctypes.c_int64), ("iterations", ctypes.c_int64), ("frame_jumps", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -74,6 +74,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise OscError(OSC_EDEVICE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch carries its own HIP runtime under the same soname as the system's:
+    # loaded first, it is the one the library's dependency resolves to, so the
+    # process holds a single runtime (loaded after the system's, torch finds
+    # no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     sig = {
@@ -448,9 +453,10 @@ class Server:
     instances given as host numpy arrays; results come back as numpy arrays."""
 
     def __init__(self, hbm_budget: int = 0, max_slots: int = 256, chunk_us: int = 0,
-                 fake_executor: bool = False):
+                 fake_executor: bool = False, frame_jumps: bool = False):
         lib = load()
-        cfg = ServerConfig(int(hbm_budget), int(max_slots), int(chunk_us), 1 if fake_executor else 0)
+        cfg = ServerConfig(int(hbm_budget), int(max_slots), int(chunk_us), 1 if fake_executor else 0,
+                           1 if frame_jumps else 0)
         h = ctypes.c_void_p()
         _check(lib.osc_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
@@ -504,7 +510,7 @@ class Server:
         _check(st)
         return {"x_frames": xf, "v_frames": vf, "x_end": xe, "v_end": ve,
                 "latency_s": info.latency_s, "queue_s": info.queue_s, "bytes": info.bytes,
-                "iterations": info.iterations}
+                "iterations": info.iterations, "frame_jumps": bool(info.frame_jumps)}
 
     def stats(self) -> dict:
         st = ServerStats()

@@ -42,12 +42,15 @@ def poisson_arrivals(n: int, qps: float, seed: int) -> np.ndarray:
 
 
 def run_stream(reqs, arrivals: Optional[np.ndarray] = None, method: str = "rk4", prec: str = "f32",
-               hbm_budget: int = 0, max_slots: int = 512, chunk_us: int = 0, timeout: float = 600.0) -> dict:
-    """arrivals: seconds after start for each request (None: all at once)."""
+               hbm_budget: int = 0, max_slots: int = 512, chunk_us: int = 0, timeout: float = 600.0,
+               frame_jumps: bool = False) -> dict:
+    """arrivals: seconds after start for each request (None: all at once).
+    frame_jumps: let the server reach a dense request's frames by powers of
+    its one-step matrix where that is much cheaper than stepping."""
     results = [None] * len(reqs)
     tickets = [None] * len(reqs)
     errors = []
-    with osc.Server(hbm_budget=hbm_budget, max_slots=max_slots, chunk_us=chunk_us) as srv:
+    with osc.Server(hbm_budget=hbm_budget, max_slots=max_slots, chunk_us=chunk_us, frame_jumps=frame_jumps) as srv:
         ready = threading.Semaphore(0)
 
         def collect():
@@ -79,6 +82,7 @@ def run_stream(reqs, arrivals: Optional[np.ndarray] = None, method: str = "rk4",
         "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
         "mean_latency_s": float(lat.mean()) if lat.size else None,
         "makespan_s": makespan, "dof_steps": int(work), "dof_steps_per_s": work / makespan,
+        "by_frame_jumps": [i for i, r in enumerate(results) if r is not None and r.get("frame_jumps")],
         "offered_qps": (len(reqs) / arrivals[-1]) if arrivals is not None and len(arrivals) else None,
         "hbm_peak_bytes": int(stats["hbm_peak"]), "iterations": int(stats["iterations"]),
         "worker_setup_s": stats["setup_s"], "worker_iterate_s": stats["iterate_s"],

@@ -186,3 +186,43 @@ def test_mixed_precisions_in_one_iteration():
             alone = srv.wait(submit(srv, reqs[i], precs[i]), timeout=120.0)
         for key in ("x_frames", "v_frames", "x_end", "v_end"):
             np.testing.assert_array_equal(alone[key], mixed[i][key])
+
+
+@pytest.mark.parametrize("method", ["rk4", "verlet"])
+def test_frame_jumps_serve_large_dense_requests(method):
+    """With frame jumps on, a dense request whose frames are far cheaper by
+    powers of its one-step matrix is served that way (the scheme's own
+    trajectory at the frames, in FP64); the others are stepped as before.
+    Every result matches the oracle, and the jump-served one is bitwise the
+    same alone and in a mix."""
+    rng = np.random.default_rng(4242)
+    M, K = workloads.random_dense_system(rng, 300)
+    dt = np.array([0.01 / workloads.dense_omega_max(M, K)])
+    big = workloads.DenseBatch(M, K, dt, rng.normal(0, 1, (1, 300)), rng.normal(0, 0.01, (1, 300)), 3000, 500,
+                               True)
+    Ms, Ks = workloads.random_dense_system(rng, 8)
+    dts = np.array([0.01 / workloads.dense_omega_max(Ms, Ks)])
+    small = workloads.DenseBatch(Ms, Ks, dts, rng.normal(0, 1, (1, 8)), rng.normal(0, 0.01, (1, 8)), 400, 100,
+                                 True)
+    chain = _stream(1, seed=77, s_max=64)[0]
+    reqs = [workloads.Request(0, 0.0, "dense", big), workloads.Request(1, 0.0, "dense", small), chain]
+    with osc.Server(max_slots=8, chunk_us=500, frame_jumps=True) as srv:
+        mixed = [srv.wait(_submit(srv, r, method), timeout=120.0) for r in reqs]
+        st = srv.stats()
+    assert st["completed"] == 3 and st["failed"] == 0
+    assert [res["frame_jumps"] for res in mixed] == [True, False, False]
+    assert mixed[0]["iterations"] == 0
+    for r, res in zip(reqs, mixed):
+        rx, rv = _oracle(r, method)
+        ex = oracle.rel_traj_err(res["x_frames"][:, None, :], rx[:, None, :])[0]
+        ev = oracle.rel_traj_err(res["v_frames"][:, None, :], rv[:, None, :])[0]
+        assert ex < 1e-5 and ev < 1e-5, (r.kind, r.system.s, ex, ev)
+        if r.system.nsteps % r.system.out_stride == 0:       # the last frame is the end state
+            np.testing.assert_array_equal(res["x_frames"][-1], res["x_end"])
+    with osc.Server(max_slots=2, frame_jumps=True) as srv:
+        alone = srv.wait(_submit(srv, reqs[0], method), timeout=120.0)
+    for key in ("x_frames", "v_frames", "x_end", "v_end"):
+        np.testing.assert_array_equal(alone[key], mixed[0][key])
+    with osc.Server(max_slots=2) as srv:               # off: the same request is stepped
+        stepped = srv.wait(_submit(srv, reqs[0], method), timeout=120.0)
+    assert not stepped["frame_jumps"] and stepped["iterations"] > 0
