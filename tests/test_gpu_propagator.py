@@ -283,3 +283,24 @@ def test_two_mass_ensemble_full_per_step_propagator(method):
     print(f"two-mass per-step propagator {method}: invariant drift max {drift.max():.3e} "
           f"p99 {np.percentile(drift, 99):.3e}")
     assert drift.max() <= 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("nsteps,stride", [(0, 10), (0, 0), (7, 100), (100, 100), (1, 0)])
+def test_dense_frame_jumps_degenerate_runs(prec, nsteps, stride):
+    """Frame jumps of s > 2 at the degenerate run lengths: no step (the
+    caller's state comes back unchanged), a stride beyond the run (frame 0
+    only, the end by the remainder power), a stride equal to the run, and a
+    single step with no frames."""
+    w = _dense(830 + nsteps, 3, 5, nsteps, stride)
+    sysm = osc.System("dense", "rk4", prec, w.M, w.K, w.dt, shared=True, batch=3).create()
+    try:
+        got = _gpu_run(sysm, w, prec, 1)
+    finally:
+        sysm.close()
+    if nsteps == 0:
+        x0, v0 = f32_inputs(w) if prec == "f32" else (w.x0, w.v0)
+        np.testing.assert_array_equal(got[2], x0)
+        np.testing.assert_array_equal(got[3], v0)
+    _check_traj(got, _oracle_for(w, "rk4", prec), 1e-6 if prec == "f32" else TOL_F64,
+                f"dense jumps {prec} nsteps={nsteps} stride={stride}")
