@@ -747,6 +747,10 @@ osc_status osc_server_submit(osc_server *srv, const osc_desc *d, const void *x0,
     r->nframes = out_stride > 0 ? nsteps / out_stride + 1 : 0;
     r->jump = S.cfg.frame_jumps != 0 && !S.cfg.fake_executor && jumps_pay(r->desc, nsteps, out_stride);
     r->bytes = estimate_bytes(r->desc, r->nframes, r->jump);
+    if (r->jump && S.cfg.hbm_budget && (size_t)r->bytes > S.cfg.hbm_budget) {   // stepping needs less
+        r->jump = false;
+        r->bytes = estimate_bytes(r->desc, r->nframes, false);
+    }
     if (S.cfg.hbm_budget && (size_t)r->bytes > S.cfg.hbm_budget) {
         delete r;
         return fail(OSC_ENOMEM, "request needs more device memory than the whole budget");

@@ -226,3 +226,11 @@ def test_frame_jumps_serve_large_dense_requests(method):
     with osc.Server(max_slots=2) as srv:               # off: the same request is stepped
         stepped = srv.wait(_submit(srv, reqs[0], method), timeout=120.0)
     assert not stepped["frame_jumps"] and stepped["iterations"] > 0
+    assert mixed[0]["bytes"] > stepped["bytes"]        # the jump temporaries are accounted
+    # a budget that holds the stepped request but not the jump temporaries:
+    # the request is stepped, not refused
+    with osc.Server(max_slots=2, frame_jumps=True, hbm_budget=stepped["bytes"]) as srv:
+        tight = srv.wait(_submit(srv, reqs[0], method), timeout=120.0)
+    assert not tight["frame_jumps"]
+    for key in ("x_frames", "v_frames", "x_end", "v_end"):
+        np.testing.assert_array_equal(tight[key], stepped[key])
