@@ -17,7 +17,10 @@
  *     four-stage RK4 (nodes 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6) with a
  *     caller-given step, and velocity Verlet (kick-drift-kick) beside it;
  *   - the energy E = 1/2 v^T M v + 1/2 x^T K x, and the discrete invariant of
- *     velocity Verlet Q = v^T M v + x^T K x - (h^2/4) (K x)^T M^-1 (K x).
+ *     velocity Verlet Q = v^T M v + x^T K x - (h^2/4) (K x)^T M^-1 (K x);
+ *   - beyond eq. (1): Rayleigh damping and a harmonic force, coupled Van der
+ *     Pol chains (the nonlinear oscillators section 1 motivates the work
+ *     with), and the adaptive Dormand-Prince pair for MATLAB's solvers (3).
  *
  * Everything is plain double-precision loops, built with -ffp-contract=off so
  * that no fused multiply-add changes the rounding.  OpenMP only spreads
@@ -461,6 +464,7 @@ int oracle_propagator(int method, int kind, int s, const double *a, const double
 typedef struct {
     double alpha, beta, omega;
     const double *f;     /* [s] or NULL */
+    double mu;           /* chains: Van der Pol coefficient (0: none) */
 } drive_t;
 
 static void accel_driven(const rhs_t *r, const drive_t *d, double t, const double *x, const double *v,
@@ -473,6 +477,12 @@ static void accel_driven(const rhs_t *r, const drive_t *d, double t, const doubl
     if (d->f) {
         const double c = cos(d->omega * t);
         for (int i = 0; i < r->s; ++i) a[i] += d->f[i] * c;
+    }
+    if (d->mu != 0.0 && r->kind == 0) {
+        /* Van der Pol element on every body of a chain: the force
+         * mu (1 - x_i^2) x_i' pumps energy in while |x_i| < 1 and takes it
+         * out beyond, which draws each body towards a limit cycle */
+        for (int i = 0; i < r->s; ++i) a[i] += d->mu * ((1.0 - x[i] * x[i]) * v[i]) / r->m[i];
     }
 }
 
@@ -561,7 +571,7 @@ int oracle_chain_driven(int64_t batch, int s, const double *m, const double *k, 
                 const double *mb = m + (size_t)b * s;
                 if (F)
                     for (int i = 0; i < s; ++i) f[i] = F[(size_t)b * s + i] / mb[i];
-                drive_t d = {alpha, beta, F ? omega[b] : 0.0, F ? f : NULL};
+                drive_t d = {alpha, beta, F ? omega[b] : 0.0, F ? f : NULL, 0.0};
                 rhs_t r = {0, s, mb, k + (size_t)b * s, NULL};
                 integrate_driven_one(&r, &d, dt[b], x0 + (size_t)b * s, v0 + (size_t)b * s, nsteps, stride,
                                      batch, b, xf, vf, xe, ve, work);
@@ -569,6 +579,40 @@ int oracle_chain_driven(int64_t batch, int s, const double *m, const double *k, 
         }
         free(work);
         free(f);
+    }
+    return fail;
+}
+
+/* Coupled Van der Pol chains (the nonlinear oscillators section 1 names as the
+ * standard model of the field): the chain of eq. (2) with a Van der Pol
+ * element on every body,
+ *     m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = 0,
+ * by classic RK4 on the first-order system (stages as above).  mu = 0 gives
+ * the free chain, by the same operations as the damped, driven integrator. */
+int oracle_chain_vdp(int64_t batch, int s, const double *m, const double *k, const double *dt, double mu,
+                     const double *x0, const double *v0, int64_t nsteps, int64_t stride, double *xf,
+                     double *vf, double *xe, double *ve) {
+    int st = check_common(ORC_RK4, batch, s, dt, x0, v0, nsteps, stride);
+    if (st) return st;
+    if (batch > 0 && (!m || !k)) return ORC_EINVAL;
+    if (!(mu >= 0.0) || !isfinite(mu)) return ORC_EINVAL;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * ORC_DRIVEN_WORK_PER_DOF * (size_t)s);
+        if (!work) {
+#pragma omp atomic write
+            fail = ORC_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t b = 0; b < batch; ++b) {
+                drive_t d = {0.0, 0.0, 0.0, NULL, mu};
+                rhs_t r = {0, s, m + (size_t)b * s, k + (size_t)b * s, NULL};
+                integrate_driven_one(&r, &d, dt[b], x0 + (size_t)b * s, v0 + (size_t)b * s, nsteps, stride,
+                                     batch, b, xf, vf, xe, ve, work);
+            }
+        }
+        free(work);
     }
     return fail;
 }
@@ -612,7 +656,7 @@ int oracle_dense_driven(int64_t batch, int s, int shared, const double *M, const
                     formed = -1;
                     continue;
                 }
-                drive_t d = {alpha, beta, F ? omega[b] : 0.0, F ? f : NULL};
+                drive_t d = {alpha, beta, F ? omega[b] : 0.0, F ? f : NULL, 0.0};
                 rhs_t r = {1, s, NULL, NULL, A};
                 integrate_driven_one(&r, &d, shared ? dt[0] : dt[b], x0 + (size_t)b * s, v0 + (size_t)b * s,
                                      nsteps, stride, batch, b, xf, vf, xe, ve, work);
@@ -642,9 +686,9 @@ int oracle_dense_driven(int64_t batch, int s, int shared, const double *M, const
  * each output time.  One instance of a chain (kind 0: a = m, b = k) or a dense
  * system (kind 1: a = M, b = K), damped and driven as above (F may be NULL).
  * xo, vo: [nout+1][s].  stats: accepted and rejected steps. */
-int oracle_dopri_driven(int kind, int s, const double *a, const double *b, double alpha, double beta,
-                        const double *F, double omega, const double *x0, const double *v0, double t_end,
-                        int nout, double rtol, double atol, double *xo, double *vo, int64_t *stats) {
+/* The integration itself, for one instance with right-hand side r and drive d. */
+static int dopri_core(const rhs_t *r, const drive_t *d, const double *x0, const double *v0, double t_end,
+                      int nout, double rtol, double atol, double *xo, double *vo, int64_t *stats) {
     static const double c2 = 1.0 / 5, c3 = 3.0 / 10, c4 = 4.0 / 5, c5 = 8.0 / 9;
     static const double a21 = 1.0 / 5;
     static const double a31 = 3.0 / 40, a32 = 9.0 / 40;
@@ -656,34 +700,18 @@ int oracle_dopri_driven(int kind, int s, const double *a, const double *b, doubl
                         a76 = 11.0 / 84;
     static const double e1 = 71.0 / 57600, e3 = -71.0 / 16695, e4 = 71.0 / 1920, e5 = -17253.0 / 339200,
                         e6 = 22.0 / 525, e7 = -1.0 / 40;
-    if ((kind != 0 && kind != 1) || s < 1 || nout < 1 || !(t_end > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) ||
-        !a || !b || !x0 || !v0 || !xo || !vo)
-        return ORC_EINVAL;
-    const int n = 2 * s;
-    const size_t ss = (size_t)s * s;
-    double *buf = (double *)calloc((size_t)n * 10 + ss * 2 + 3 * (size_t)s, sizeof(double));
+    const int s = r->s, n = 2 * s;
+    double *buf = (double *)calloc((size_t)n * 10 + (size_t)s, sizeof(double));
     if (!buf) return ORC_ENOMEM;
     double *y = buf, *yn = y + n, *yt = yn + n, *k[7];
     for (int q = 0; q < 7; ++q) k[q] = yt + n + (size_t)q * n;
-    double *A = k[6] + n, *L = A + ss, *f = L + ss, *tmp = f + s, *yy = tmp + s;
-    rhs_t r;
+    double *tmp = k[6] + n;
     int st = ORC_OK;
-    if (kind == 1) {
-        st = oracle_form_a(s, a, b, A);
-        if (!st && F) st = solve_spd(s, a, F, f, L, yy);
-        r = (rhs_t){1, s, NULL, NULL, A};
-    } else {
-        if (F)
-            for (int i = 0; i < s; ++i) f[i] = F[i] / a[i];
-        r = (rhs_t){0, s, a, b, NULL};
-    }
-    if (st) { free(buf); return st; }
-    drive_t d = {alpha, beta, omega, F ? f : NULL};
     /* derivative of the first-order state z = (x, v) */
 #define DERIV(t_, z_, out_)                                                   \
     do {                                                                      \
         memcpy((out_), (z_) + s, sizeof(double) * s);                         \
-        accel_driven(&r, &d, (t_), (z_), (z_) + s, (out_) + s, tmp);          \
+        accel_driven(r, d, (t_), (z_), (z_) + s, (out_) + s, tmp);          \
     } while (0)
     memcpy(y, x0, sizeof(double) * s);
     memcpy(y + s, v0, sizeof(double) * s);
@@ -742,4 +770,44 @@ int oracle_dopri_driven(int kind, int s, const double *a, const double *b, doubl
     if (stats) { stats[0] = acc; stats[1] = rej; }
     free(buf);
     return st;
+}
+
+int oracle_dopri_driven(int kind, int s, const double *a, const double *b, double alpha, double beta,
+                        const double *F, double omega, const double *x0, const double *v0, double t_end,
+                        int nout, double rtol, double atol, double *xo, double *vo, int64_t *stats) {
+    if ((kind != 0 && kind != 1) || s < 1 || nout < 1 || !(t_end > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) ||
+        !a || !b || !x0 || !v0 || !xo || !vo)
+        return ORC_EINVAL;
+    const size_t ss = (size_t)s * s;
+    double *buf = (double *)calloc(ss * 2 + 2 * (size_t)s, sizeof(double));
+    if (!buf) return ORC_ENOMEM;
+    double *A = buf, *L = A + ss, *f = L + ss, *yy = f + s;
+    rhs_t r;
+    int st = ORC_OK;
+    if (kind == 1) {
+        st = oracle_form_a(s, a, b, A);
+        if (!st && F) st = solve_spd(s, a, F, f, L, yy);
+        r = (rhs_t){1, s, NULL, NULL, A};
+    } else {
+        if (F)
+            for (int i = 0; i < s; ++i) f[i] = F[i] / a[i];
+        r = (rhs_t){0, s, a, b, NULL};
+    }
+    if (!st) {
+        drive_t d = {alpha, beta, omega, F ? f : NULL, 0.0};
+        st = dopri_core(&r, &d, x0, v0, t_end, nout, rtol, atol, xo, vo, stats);
+    }
+    free(buf);
+    return st;
+}
+
+/* The same adaptive reference for one Van der Pol chain (m, k [s], mu). */
+int oracle_dopri_vdp(int s, const double *m, const double *k, double mu, const double *x0, const double *v0,
+                     double t_end, int nout, double rtol, double atol, double *xo, double *vo, int64_t *stats) {
+    if (s < 1 || nout < 1 || !(t_end > 0.0) || !(rtol > 0.0) || !(atol >= 0.0) || !(mu >= 0.0) ||
+        !isfinite(mu) || !m || !k || !x0 || !v0 || !xo || !vo)
+        return ORC_EINVAL;
+    rhs_t r = {0, s, m, k, NULL};
+    drive_t d = {0.0, 0.0, 0.0, NULL, mu};
+    return dopri_core(&r, &d, x0, v0, t_end, nout, rtol, atol, xo, vo, stats);
 }

@@ -1,0 +1,166 @@
+"""Pins of the oracle's coupled Van der Pol chains (the nonlinear oscillators
+the paper's section 1 names as the standard model of the field):
+m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = 0 with the chain's K.
+
+The system has no closed form, so each check compares the oracle with
+something fixed another way: the free chain at mu = 0, the energy balance
+dE/dt = mu sum_i (1 - x_i^2) v_i^2 along the trajectory, the amplitude law
+of first-order averaging at small mu, the period of the limit cycle at
+mu = 1 and mu = 10 (classical values), and fourth-order convergence to the
+adaptive Dormand-Prince reference.  A dropped or sign-flipped term, a missing
+mass, or a wrong stage weight each fail at least one of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_02207_amd import workloads
+
+
+def _chain(seed, batch, s):
+    rng = np.random.default_rng(seed)
+    m, k = workloads.random_chain(rng, batch, s)
+    dt = 0.01 / workloads.chain_omega_max(m, k)
+    x0 = rng.normal(0.0, 1.0, (batch, s))
+    v0 = rng.normal(0.0, 1.0, (batch, s)) * np.sqrt(k.mean(axis=1, keepdims=True) / m.mean(axis=1, keepdims=True))
+    return m, k, dt, x0, v0
+
+
+def test_mu_zero_is_the_free_chain():
+    """mu = 0: the same operations as the damped, driven integrator with no
+    damping and no force (bitwise), and the free RK4 chain (up to rounding)."""
+    m, k, dt, x0, v0 = _chain(1, 3, 5)
+    got = oracle.chain_vdp(m, k, dt, 0.0, x0, v0, 500, 100)
+    drv = oracle.chain_driven(m, k, dt, 0.0, 0.0, None, 0.0, x0, v0, 500, 100)
+    free = oracle.chain("rk4", m, k, dt, x0, v0, 500, 100)
+    for a, b in zip(got, drv):
+        np.testing.assert_array_equal(a, b)
+    assert oracle.rel_traj_err(got[0], free[0]).max() < 1e-12
+    assert oracle.rel_traj_err(got[1], free[1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("mu", [0.3, 2.0])
+def test_energy_balance_along_the_trajectory(mu):
+    """E = 1/2 v^T M v + 1/2 x^T K x changes only by the Van der Pol elements'
+    power mu sum_i (1 - x_i^2) v_i^2 (the springs conserve it): E(T) - E(0)
+    equals that power integrated over the frames by Simpson's rule, to the
+    order of both (h^4)."""
+    rng = np.random.default_rng(7)
+    s, h, n = 3, 2e-3, 5000
+    m = rng.uniform(0.5, 2.0, (1, s))
+    k = rng.uniform(0.5, 2.0, (1, s))
+    x0 = rng.normal(0.0, 1.0, (1, s))
+    v0 = rng.normal(0.0, 1.0, (1, s))
+    xf, vf, _, _ = oracle.chain_vdp(m, k, np.array([h]), mu, x0, v0, n, 1)
+    x, v = xf[:, 0], vf[:, 0]
+    E = oracle.energy_chain(np.repeat(m, n + 1, 0), np.repeat(k, n + 1, 0), x, v)
+    P = mu * ((1.0 - x * x) * v * v).sum(axis=1)
+    work = h / 3.0 * (P[0] + P[-1] + 4.0 * P[1:-1:2].sum() + 2.0 * P[2:-1:2].sum())
+    dE = E[-1] - E[0]
+    print(f"mu={mu}: dE {dE:.12e}, integrated power {work:.12e}")
+    assert abs(dE - work) < 1e-8 * max(abs(dE), E.max())
+    # a sign error in the element would send E the other way: check it moved
+    assert abs(dE) > 1e-3 * E.max()
+
+
+def test_small_mu_amplitude_follows_averaging():
+    """One body (m = k = 1), mu = 0.05, from amplitude 0.5: first-order
+    averaging gives a(t) = 2 / sqrt(1 + (4/a0^2 - 1) exp(-mu t)); the
+    amplitude sqrt(x^2 + v^2), averaged over a period, follows it to O(mu^2)."""
+    mu, h, a0 = 0.05, 1e-2, 0.5
+    n = 20000
+    one = np.array([[1.0]])
+    xf, vf, _, _ = oracle.chain_vdp(one, one, np.array([h]), mu, np.array([[a0]]), np.array([[0.0]]), n, 1)
+    amp = np.hypot(xf[:, 0, 0], vf[:, 0, 0])
+    half = int(np.pi / h)
+    for t in (20.0, 50.0, 100.0, 150.0, 190.0):
+        i = int(round(t / h))
+        avg = amp[i - half:i + half].mean()
+        ref = 2.0 / np.sqrt(1.0 + (4.0 / a0 ** 2 - 1.0) * np.exp(-mu * t))
+        assert abs(avg - ref) < 3e-3, (t, avg, ref)
+
+
+@pytest.mark.parametrize("mu,period,tol", [(1.0, 6.6632868593, 2e-7), (10.0, 19.0784, 1e-4)])
+def test_limit_cycle_period(mu, period, tol):
+    """One body (m = k = 1): the period of the limit cycle, from the upward
+    zero crossings after the transient (each refined by one Newton step from
+    the nearest frame), against the classical values 6.66328686 (mu = 1) and
+    19.0784 (mu = 10)."""
+    h = 1e-3
+    n = int(round(12 * period / h))
+    one = np.array([[1.0]])
+    xf, vf, _, _ = oracle.chain_vdp(one, one, np.array([h]), mu, np.array([[2.0]]), np.array([[0.0]]), n, 1)
+    x, v = xf[:, 0, 0], vf[:, 0, 0]
+    i = np.where((x[:-1] < 0.0) & (x[1:] >= 0.0))[0] + 1
+    tc = i * h - x[i] / v[i]
+    per = np.diff(tc)[-3:]
+    print(f"mu={mu}: periods {per}")
+    assert np.all(np.abs(per / period - 1.0) < tol)
+
+
+def test_rk4_converges_to_the_adaptive_reference():
+    """A coupled chain of three Van der Pol bodies: the fixed-step RK4 error
+    against Dormand-Prince 5(4) at rtol 1e-12 falls 16-fold per halving of
+    the step (fourth order), and is below 2e-8 at the finest step (h = 5e-3)."""
+    rng = np.random.default_rng(11)
+    s, mu, T = 3, 0.8, 10.0
+    m = rng.uniform(0.5, 2.0, s)
+    k = rng.uniform(0.5, 2.0, s)
+    x0 = rng.normal(0.0, 1.0, s)
+    v0 = rng.normal(0.0, 1.0, s)
+    xr, vr, acc, rej = oracle.dopri_vdp(m, k, mu, x0, v0, T, 1, rtol=1e-12, atol=1e-14)
+    errs = []
+    for n in (250, 500, 1000, 2000):
+        _, _, xe, ve = oracle.chain_vdp(m[None], k[None], np.array([T / n]), mu, x0[None], v0[None], n, 0,
+                                        frames=False)
+        errs.append(max(np.abs(xe[0] - xr[-1]).max(), np.abs(ve[0] - vr[-1]).max()))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    print("errors", errs, "ratios", ratios)
+    assert all(13.0 < r < 19.0 for r in ratios)
+    assert errs[-1] < 2e-8
+
+
+VDP_MUTANTS = [
+    ("a[i] += d->mu * ((1.0 - x[i] * x[i]) * v[i]) / r->m[i];",
+     "a[i] -= d->mu * ((1.0 - x[i] * x[i]) * v[i]) / r->m[i];"),     # sign
+    ("a[i] += d->mu * ((1.0 - x[i] * x[i]) * v[i]) / r->m[i];",
+     "a[i] += d->mu * ((1.0 - x[i] * x[i]) * v[i]);"),               # mass dropped
+    ("a[i] += d->mu * ((1.0 - x[i] * x[i]) * v[i]) / r->m[i];",
+     "a[i] += d->mu * ((1.0 - x[i]) * v[i]) / r->m[i];"),            # wrong nonlinearity
+]
+
+
+@pytest.mark.parametrize("orig,mut", VDP_MUTANTS)
+def test_pins_catch_planted_vdp_mistakes(orig, mut, tmp_path):
+    """Recompile the oracle with one plausible mistake in the Van der Pol
+    element and check that the energy balance rejects it (CPU only)."""
+    import ctypes
+    import os
+    import subprocess
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "osc_oracle.c")).read()
+    assert src.count(orig) == 1
+    mpath = tmp_path / "mut.c"
+    mpath.write_text(src.replace(orig, mut))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(lib), str(mpath), "-lm"], check=True)
+    L = ctypes.CDLL(str(lib))
+    d = ctypes.POINTER(ctypes.c_double)
+    L.oracle_chain_vdp.argtypes = [ctypes.c_int64, ctypes.c_int, d, d, d, ctypes.c_double, d, d, ctypes.c_int64,
+                                   ctypes.c_int64, d, d, d, d]
+    rng = np.random.default_rng(7)
+    s, h, n, mu = 3, 2e-3, 5000, 0.3
+    m = np.ascontiguousarray(rng.uniform(0.5, 2.0, (1, s)))
+    k = np.ascontiguousarray(rng.uniform(0.5, 2.0, (1, s)))
+    x0 = np.ascontiguousarray(rng.normal(0.0, 1.0, (1, s)))
+    v0 = np.ascontiguousarray(rng.normal(0.0, 1.0, (1, s)))
+    hh = np.array([h])
+    xf, vf = np.empty((n + 1, 1, s)), np.empty((n + 1, 1, s))
+    xe, ve = np.empty((1, s)), np.empty((1, s))
+    p = lambda a: a.ctypes.data_as(d)
+    assert L.oracle_chain_vdp(1, s, p(m), p(k), p(hh), mu, p(x0), p(v0), n, 1, p(xf), p(vf), p(xe), p(ve)) == 0
+    x, v = xf[:, 0], vf[:, 0]
+    E = oracle.energy_chain(np.repeat(m, n + 1, 0), np.repeat(k, n + 1, 0), x, v)
+    P = mu * ((1.0 - x * x) * v * v).sum(axis=1)
+    work = h / 3.0 * (P[0] + P[-1] + 4.0 * P[1:-1:2].sum() + 2.0 * P[2:-1:2].sum())
+    assert abs((E[-1] - E[0]) - work) > 1e-8 * max(abs(E[-1] - E[0]), E.max()), "planted mistake not detected"
