@@ -650,6 +650,27 @@ osc_status integrate_driven(osc_sys *s, const void *x0, const void *v0, int64_t 
     return run_chunks(s, a, nsteps, [&](const DrivenLaunch<T> &c) { return driven_launch<T>(c, s->stream); });
 }
 
+// Van der Pol chains (osc_set_van_der_pol): stage-form RK4 in registers.
+template <typename T>
+osc_status integrate_vdp(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride, void *xf,
+                         void *vf, void *xe, void *ve) {
+    VdpLaunch<T> a{};
+    a.batch = s->batch;
+    a.s = s->s;
+    a.c = coef_of<T>(s);
+    a.m = s->m;
+    a.mu = s->vdp_mu;
+    a.x0 = static_cast<const T *>(x0);
+    a.v0 = static_cast<const T *>(v0);
+    a.out_stride = out_stride;
+    a.xf = static_cast<T *>(xf);
+    a.vf = static_cast<T *>(vf);
+    a.xe = static_cast<T *>(xe);
+    a.ve = static_cast<T *>(ve);
+    a.nonfinite = s->flag;
+    return run_chunks(s, a, nsteps, [&](const VdpLaunch<T> &c) { return vdp_launch<T>(c, s->stream); });
+}
+
 }  // namespace
 
 template <typename T>
@@ -797,6 +818,8 @@ osc_status osc_set_config(osc_sys *s, osc_config key, int64_t value) {
             return OSC_OK;
         case OSC_CFG_PROPAGATOR:
             if (value < 0 || value > 2) return fail(OSC_EINVAL, "propagator mode must be 0, 1 or 2");
+            if (value != 0 && s->vdp_mu > 0.0)
+                return fail(OSC_ENOTSUP, "the propagator modes take linear systems, not Van der Pol chains");
             if (value == 2 && !(s->kind == OSC_CHAIN && s->s <= 2))
                 return fail(OSC_ENOTSUP, "the per-step propagator takes chains of s <= 2");
             s->propagator = (int)value;
@@ -817,6 +840,9 @@ static osc_status integrate_checks(osc_sys *s, const void *x0, const void *v0, i
 
 static osc_status integrate_any(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, int64_t out_stride,
                                 void *xf, void *vf, void *xe, void *ve) {
+    if (s->vdp_mu > 0.0)
+        return s->prec == OSC_F32 ? integrate_vdp<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
+                                  : integrate_vdp<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
     if (s->driven)
         return s->prec == OSC_F32 ? integrate_driven<float>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve)
                                   : integrate_driven<double>(s, x0, v0, nsteps, out_stride, xf, vf, xe, ve);
@@ -885,7 +911,8 @@ osc_status osc_integrate_static(osc_sys *s, const void *x0, const void *v0, int6
 osc_status osc_integrate_plain(osc_sys *s, const void *x0, const void *v0, int64_t nsteps, void *xe, void *ve) {
     g_last_error.clear();
     if (!s) return fail(OSC_EINVAL, "handle is NULL");
-    if (s->driven) return fail(OSC_ENOTSUP, "the plain baseline takes free (undamped, undriven) systems");
+    if (s->driven || s->vdp_mu > 0.0)
+        return fail(OSC_ENOTSUP, "the plain baseline takes free (undamped, undriven, linear) systems");
     if (nsteps < 0) return fail(OSC_EINVAL, "nsteps must be >= 0");
     if (s->batch == 0) return OSC_OK;
     if (!x0 || !v0) return fail(OSC_EINVAL, "x0 and v0 must be non-NULL");
@@ -934,6 +961,8 @@ osc_status osc_set_excitation(osc_sys *s, double alpha, double beta, const doubl
     const bool on = alpha != 0.0 || beta != 0.0 || F != nullptr;
     if (on && s->method != OSC_RK4)
         return fail(OSC_ENOTSUP, "damped / driven systems are integrated by RK4 only");
+    if (on && s->vdp_mu > 0.0)
+        return fail(OSC_ENOTSUP, "a handle is either damped / driven or a Van der Pol chain, not both");
     const hipStream_t st = s->stream;
     const int64_t nh = s->kind == OSC_CHAIN ? s->batch : s->nsys;
     if ((alpha != 0.0 || beta != 0.0) && nh > 0) {
@@ -984,10 +1013,26 @@ osc_status osc_set_excitation(osc_sys *s, double alpha, double beta, const doubl
     return OSC_OK;
 }
 
+osc_status osc_set_van_der_pol(osc_sys *s, double mu) {
+    g_last_error.clear();
+    if (!s) return fail(OSC_EINVAL, "handle is NULL");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(OSC_EINVAL, "mu must be finite and >= 0");
+    if (mu > 0.0) {
+        if (s->kind != OSC_CHAIN) return fail(OSC_ENOTSUP, "Van der Pol elements are on chains only");
+        if (s->method != OSC_RK4) return fail(OSC_ENOTSUP, "Van der Pol chains are integrated by RK4 only");
+        if (s->s > 1024) return fail(OSC_ENOTSUP, "Van der Pol chains take s <= 1024");
+        if (s->driven) return fail(OSC_ENOTSUP, "a handle is either damped / driven or a Van der Pol chain, not both");
+        if (s->propagator) return fail(OSC_ENOTSUP, "the propagator modes take linear systems, not Van der Pol chains");
+    }
+    s->vdp_mu = mu;
+    return OSC_OK;
+}
+
 osc_status osc_propagator(osc_sys *s, int64_t k, double *P) {
     g_last_error.clear();
     if (!s || !P) return fail(OSC_EINVAL, "handle and P must be non-NULL");
     if (k < 0) return fail(OSC_EINVAL, "k must be >= 0");
+    if (s->vdp_mu > 0.0) return fail(OSC_ENOTSUP, "a Van der Pol chain has no step matrix (nonlinear)");
     if (s->batch == 0) return OSC_OK;
     return propagator_matrix(prop_args(s), s->s, k, P, s->stream);
 }
@@ -1037,6 +1082,7 @@ osc_status sys_rt_supported(const osc_sys *s) {
 
 osc_status sys_rt_resident_supported(const osc_sys *s) {
     if (s->kind != OSC_CHAIN) return fail(OSC_ENOTSUP, "resident real-time stepping takes chains only");
+    if (s->vdp_mu > 0.0) return fail(OSC_ENOTSUP, "resident real-time stepping takes linear chains");
     if (s->driven && (s->s > 1024 || s->dense_kernel == 1))
         return fail(OSC_ENOTSUP, "resident real-time stepping of damped or driven chains takes the register "
                                  "kernels (s <= 1024)");

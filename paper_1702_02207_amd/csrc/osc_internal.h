@@ -422,6 +422,27 @@ template <typename T>
 osc_status driven_launch(const DrivenLaunch<T> &a, hipStream_t st);
 // f = F / m (chains, [n] elements)
 osc_status chain_force(int64_t n, const double *F, const double *m, double *f, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// coupled Van der Pol chains (vdp.hip): m_i x_i'' - mu (1 - x_i^2) x_i' +
+// (K x)_i = 0, classic RK4 in stage form, s <= 1024 (register layouts)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct VdpLaunch {
+    int64_t batch;
+    int32_t s;
+    ChainCoef<T> c;
+    const double *m;           // [batch][s] masses
+    double mu;
+    const T *x0, *v0;
+    T *state;                  // [4][batch][s] as for chains
+    int64_t nsteps, n0, out_stride;
+    T *xf, *vf, *xe, *ve;
+    int *nonfinite;
+    int load_mode, store_mode;
+};
+template <typename T>
+osc_status vdp_launch(const VdpLaunch<T> &a, hipStream_t st);
 // f_b = M^-1 F_b for dense systems (M^-1 by the Cholesky formation with K = I)
 osc_status dense_force(int s, int64_t nsys, int64_t batch, const double *M, const double *F, double *f,
                        int *notspd, hipStream_t st);
@@ -502,6 +523,8 @@ struct osc_sys {
     double alpha = 0.0, beta = 0.0;
     double *force = nullptr;             // [batch][s] M^-1 F (device), or nullptr
     double *omega = nullptr;             // [batch] (device)
+    // osc_set_van_der_pol: a Van der Pol element on every body (chains, RK4)
+    double vdp_mu = 0.0;
     // real-time stepping (osc_rt_tick): the next integration is one launch
     // from global step rt_n0 that loads the held state (or the given initial
     // state when rt_load == LOAD_USER) and stores it back beside the output

@@ -92,6 +92,7 @@ def load():
         "osc_dense_operator": (i32, [vp, vp]),
         "osc_propagator": (i32, [vp, i64, vp]),
         "osc_set_excitation": (i32, [vp, ctypes.c_double, ctypes.c_double, vp, vp, i32]),
+        "osc_set_van_der_pol": (i32, [vp, ctypes.c_double]),
         "osc_rt_create": (i32, [vp, vp, vp, i64, ctypes.POINTER(vp)]),
         "osc_rt_tick": (i32, [vp, vp, vp]),
         "osc_rt_steps": (i64, [vp]),
@@ -327,6 +328,13 @@ class System:
         _check(load().osc_set_excitation(self.handle, float(alpha), float(beta), Fp, Wp, mem))
         return self
 
+    def set_van_der_pol(self, mu: float):
+        """osc_set_van_der_pol: a Van der Pol element mu (1 - x_i^2) x_i' on
+        every body of a chain (mu = 0: linear again)."""
+        if self.handle is None:
+            raise ValueError("the system has not been created (call create())")
+        _check(load().osc_set_van_der_pol(self.handle, float(mu)))
+        return self
     def propagator(self, k: int = 1):
         """osc_propagator: the FP64 matrix of k steps on (x, v), a new device
         tensor [nsys, 2s, 2s] (nsys = batch, or 1 for a shared operator)."""

@@ -1,0 +1,160 @@
+"""Coupled Van der Pol chains (osc_set_van_der_pol) through the C ABI against
+the FP64 oracle: every register layout in FP32 and FP64, chunked and
+allocation-free runs bit for bit equal to one launch, real-time ticks equal
+to the frames of one integration, and the combinations the entry point
+refuses."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_02207_amd import osc, workloads
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-10}
+
+
+def _vdp(seed, batch, s, nsteps, stride):
+    """Random chains (masses U[0.5, 2], springs log-U[1e2, 1e4]), dt = 0.01 /
+    omega_max, x0 ~ N(0, 1), v0 = 0, and mu of the order of the chains'
+    frequencies, so that the elements shape the motion within the run."""
+    rng = np.random.default_rng(seed)
+    m, k = workloads.random_chain(rng, batch, s)
+    wmax = workloads.chain_omega_max(m, k)
+    dt = 0.01 / wmax
+    mu = float(0.2 * np.median(wmax))
+    x0 = rng.normal(0.0, 1.0, (batch, s))
+    v0 = np.zeros((batch, s))
+    return m, k, dt, mu, x0, v0
+
+
+def _run(sysm, x0, v0, nsteps, stride, prec, static=False):
+    import torch
+    dt = torch.float32 if prec == "f32" else torch.float64
+    out = sysm.integrate(to_dev(x0, dt), to_dev(v0, dt), nsteps, stride, static=static)
+    sysm.sync()
+    return [t.double().cpu().numpy() for t in out]
+
+
+def _inputs(x0, v0, prec):
+    if prec == "f32":
+        return x0.astype(np.float32).astype(np.float64), v0.astype(np.float32).astype(np.float64)
+    return x0, v0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("s,batch", [(1, 33), (2, 40), (5, 9), (8, 70), (37, 3), (64, 2), (100, 3), (300, 2),
+                                     (700, 2), (1024, 2)])
+def test_vdp_chains_match_oracle(s, batch, prec):
+    """Every register layout (one lane per chain for s <= 8, one wave per
+    chain beyond; ragged runs at s = 5, 37, 100, 300, 700) against the
+    oracle's stage-form RK4, frames and end state."""
+    nsteps, stride = 1500, 250
+    m, k, dt, mu, x0, v0 = _vdp(900 + s, batch, s, nsteps, stride)
+    sysm = osc.System("chain", "rk4", prec, m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(mu)
+        xf, vf, xe, ve = _run(sysm, x0, v0, nsteps, stride, prec)
+    finally:
+        sysm.close()
+    x0r, v0r = _inputs(x0, v0, prec)
+    rx, rv, rxe, rve = oracle.chain_vdp(m, k, dt, mu, x0r, v0r, nsteps, stride)
+    ex, ev = oracle.rel_traj_err(xf, rx).max(), oracle.rel_traj_err(vf, rv).max()
+    print(f"vdp s={s} {prec}: x {ex:.2e} v {ev:.2e}")
+    assert max(ex, ev) < TOL[prec]
+    np.testing.assert_array_equal(xf[-1], xe)
+    np.testing.assert_array_equal(vf[-1], ve)
+    # the elements matter in this run: the linear chain ends elsewhere
+    lx, _, _, _ = oracle.chain("rk4", m, k, dt, x0r, v0r, nsteps, stride)
+    assert oracle.rel_traj_err(lx, rx).max() > 100 * TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_vdp_chunked_and_static_runs_are_bitwise_one_launch(prec):
+    """The compensated state passes between launches: chunks of 333 steps,
+    and the allocation-free entry with the same chunks, give the bits of one
+    launch."""
+    m, k, dt, mu, x0, v0 = _vdp(950, 4, 300, 1200, 200)
+    sysm = osc.System("chain", "rk4", prec, m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(mu)
+        whole = _run(sysm, x0, v0, 1200, 200, prec)
+        sysm.set_config(osc.CFG_STEPS_PER_LAUNCH, 333)
+        chunked = _run(sysm, x0, v0, 1200, 200, prec)
+        static = _run(sysm, x0, v0, 1200, 200, prec, static=True)
+    finally:
+        sysm.close()
+    for a, b, c in zip(whole, chunked, static):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, c)
+
+
+def test_vdp_real_time_ticks_are_the_frames_of_one_integration():
+    """The launch-per-tick real-time stepper on a Van der Pol pair (the two
+    coupled oscillators of the paper's section 1, FP64): the states after the
+    ticks equal the frames of one osc_integrate call bit for bit."""
+    import torch
+    m, k, dt, mu, x0, v0 = _vdp(960, 1, 2, 400, 4)
+    sysm = osc.System("chain", "rk4", "f64", m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(mu)
+        X0, V0 = to_dev(x0, torch.float64), to_dev(v0, torch.float64)
+        xf, vf, _, _ = sysm.integrate(X0, V0, 400, 4)
+        sysm.sync()
+        ref_x, ref_v = xf[1:].cpu().numpy(), vf[1:].cpu().numpy()
+        with osc.Realtime(sysm, X0, V0, 4) as rt:
+            tx, tv, lat, stats = rt.run(100e-6, 100)
+            tx, tv = tx.cpu().numpy(), tv.cpu().numpy()
+        with pytest.raises(osc.OscError) as e:
+            with osc.Realtime(sysm, X0, V0, 4) as rt:
+                rt.run_resident(100e-6, 10)
+        assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        sysm.close()
+    np.testing.assert_array_equal(tx, ref_x)
+    np.testing.assert_array_equal(tv, ref_v)
+    assert stats["ticks"] == 100
+
+
+def test_vdp_rejects_what_it_does_not_cover():
+    import torch
+    m, k, dt, mu, x0, v0 = _vdp(970, 2, 5, 10, 0)
+    vsys = osc.System("chain", "verlet", "f32", m, k, dt).create()
+    try:
+        with pytest.raises(osc.OscError) as e:      # Verlet
+            vsys.set_van_der_pol(mu)
+        assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        vsys.close()
+    rng = np.random.default_rng(1)
+    M, K = workloads.random_dense_system(rng, 6)
+    dsys = osc.System("dense", "rk4", "f32", M, K, np.array([0.01]), shared=True, batch=2).create()
+    try:
+        with pytest.raises(osc.OscError) as e:      # dense
+            dsys.set_van_der_pol(mu)
+        assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        dsys.close()
+    sysm = osc.System("chain", "rk4", "f32", m, k, dt).create()
+    try:
+        for bad in (-1.0, float("nan"), float("inf")):
+            with pytest.raises(osc.OscError) as e:
+                sysm.set_van_der_pol(bad)
+            assert e.value.status == osc.OSC_EINVAL
+        sysm.set_van_der_pol(mu)
+        X0 = to_dev(x0, torch.float32)
+        for call in (lambda: sysm.set_excitation(0.1, 0.0),
+                     lambda: sysm.set_config(osc.CFG_PROPAGATOR, 1),
+                     lambda: sysm.propagator(3),
+                     lambda: sysm.integrate_plain(X0, X0, 10)):
+            with pytest.raises(osc.OscError) as e:
+                call()
+            assert e.value.status == osc.OSC_ENOTSUP
+        sysm.set_van_der_pol(0.0)                   # linear again: the free integrator
+        sysm.set_excitation(0.1, 0.0)
+        with pytest.raises(osc.OscError) as e:
+            sysm.set_van_der_pol(mu)
+        assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        sysm.close()
