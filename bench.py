@@ -5,7 +5,7 @@ Default workload (c3): 4096 fixed-free spring chains of s = 1024 bodies
 (eq. (2) generalised), masses U[0.5, 2], springs LogU[1e2, 1e4],
 x0 ~ N(0, sigma = 0.1), v0 = 0, dt = 0.01/omega_max per chain, 10^5 classic
 RK4 steps with FP32 state (synthetic, seeded): the largest configuration
-that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c3d, c4, c4v, c4d, c5;
+that fits one GPU.  --workload picks another (c1, c2, c2v, c3v, c3d, c3n, c4, c4v, c4d, c5;
 and the propagator modes: c1p and c2p, the per-step step matrix; c2j and c4j, frames
 by powers of the step matrix).
 
@@ -63,7 +63,7 @@ DENSE_PRODUCTS = {"rk4": 4, "verlet": 1}
 DENSE_HW_TERMS = {"rk4": 7, "verlet": 3}     # MFMA products per step with the FP16 splits
 
 # oracle sample sizes (instance 0, the last instance and seeded others)
-CPU_SAMPLE = {"c1": 1, "c1p": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c3d": 32,
+CPU_SAMPLE = {"c1": 1, "c1p": 1, "c2": 65536, "c2v": 65536, "c2p": 65536, "c2j": 65536, "c3": 32, "c3v": 32, "c3d": 32, "c3n": 32,
               "c4": 256, "c4v": 256, "c4j": 256}
 # the per-step propagator's own count for two-mass RK4 at FP32: per DOF, dx
 # from the low parts, the w terms and the high parts of one row of the 4x4
@@ -80,6 +80,16 @@ ALG_DRIVEN_CHAIN_FLOPS = 85
 # of the recursion with their low-part sums (9 + 10 + 8 + 8) and the two
 # Kahan updates (7)
 IMPL_DRIVEN_CHAIN_FLOPS = 66
+# classic stage-form RK4 of the Van der Pol chain (FMA = 2): per stage the
+# stencil product B X (5), the slope -B X + g (1 - X^2) W (5) and the next
+# stage's arguments (4); four stages less the first one's arguments, plus the
+# weighted combination (9)
+ALG_VDP_CHAIN_FLOPS = 61
+# the register kernel's form (FMA = 2): B x with split coefficients (8), three
+# high-coefficient stencils of the offsets (4 each), the four slopes with
+# their offsets and running sums (5 + 1, 13, 13, 11), the stage inputs (2)
+# and the two Kahan updates (13)
+IMPL_VDP_CHAIN_FLOPS = 78
 
 WORKLOADS = {
     "c1": dict(kind="chain", method="rk4", prec="f64",
@@ -111,6 +121,9 @@ WORKLOADS = {
     "c3d": dict(kind="chain", method="rk4", prec="f32", driven=True,
                 desc="fixed-free spring chain: 4096 instances, s=1024, 1e4 RK4 steps, FP32, Rayleigh damping "
                      "(alpha=0.05, beta=1e-5) and a harmonic force per chain"),
+    "c3n": dict(kind="chain", method="rk4", prec="f32", vdp=True,
+                desc="coupled Van der Pol chains: the C3 chains (4096 instances, s=1024) with mu=20, 1e4 RK4 "
+                     "steps, FP32"),
     "c4d": dict(kind="dense", method="rk4", prec="f32", driven=True,
                 desc="dense eq. (1), s=256, one A shared by 8192 instances, 1e4 RK4 steps, FP32, Rayleigh damping "
                      "(alpha=0.02, beta=1e-3) and a harmonic force per instance (FP16 split MFMA)"),
@@ -131,6 +144,10 @@ def make_workload(name):
         w = workloads.c2_two_dof_ensemble()
         w.out_stride = 100 if name == "c2j" else w.nsteps
         return w
+    if name == "c3n":
+        w, mu = workloads.c3_vdp_chain()
+        w.vdp_mu = mu
+        return w
     if name == "c3d":
         w, ex = workloads.c3_driven_chain()
         w.excitation = ex
@@ -150,13 +167,14 @@ def make_workload(name):
 
 # kernel sources that decide the dominant kernel of each workload family
 TRAFFIC_SOURCES = {"chain": ("chain.hip", "chain_run.h", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h"),
-                   "driven": ("driven.hip", "driven_run.h", "osc_internal.h")}
+                   "driven": ("driven.hip", "driven_run.h", "osc_internal.h"), "vdp": ("vdp.hip", "osc_internal.h")}
 
 
 def src_hash(workload):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1702_02207_amd", "csrc")
-    kind = "dense" if workload.startswith("c4") else "driven" if workload == "c3d" else "chain"
+    kind = ("dense" if workload.startswith("c4") else "driven" if workload == "c3d" else
+            "vdp" if workload == "c3n" else "chain")
     for f in TRAFFIC_SOURCES[kind]:
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
@@ -200,7 +218,9 @@ def cpu_baseline(w, kind, method, prec, idx):
         v0 = v0.astype(np.float32).astype(np.float64)
     threads = host_threads()
     t0 = time.perf_counter()
-    if getattr(w, "excitation", None) is not None:
+    if getattr(w, "vdp_mu", None) is not None:
+        xf, vf, _, _ = oracle.chain_vdp(sub.m, sub.k, sub.dt, w.vdp_mu, x0, v0, w.nsteps, w.out_stride)
+    elif getattr(w, "excitation", None) is not None:
         ex = w.excitation.subset(idx)
         if kind == "chain":
             xf, vf, _, _ = oracle.chain_driven(sub.m, sub.k, sub.dt, ex.alpha, ex.beta, ex.F, ex.omega, x0, v0,
@@ -283,6 +303,8 @@ def bench_batched(args, name, spec):
         if spec.get("driven"):
             ex = w.excitation
             sysm.set_excitation(ex.alpha, ex.beta, ex.F, ex.omega)
+        if spec.get("vdp"):
+            sysm.set_van_der_pol(w.vdp_mu)
         return sysm
 
     def one_step(record):
@@ -330,6 +352,14 @@ def bench_batched(args, name, spec):
                         frac=round(achieved / peak, 4), traffic=measured_traffic(name),
                         kernel="dense_mfma_kernel (damped, driven)", kernel_ms=round(kavg * 1e3, 4),
                         flops_per_dof_step=fpd, hw_mfma_tflops=round(hw, 1), hw_mfma_frac=round(hw / peak, 4))
+    elif spec.get("vdp"):
+        fpd = ALG_VDP_CHAIN_FLOPS
+        achieved = fpd * dof_steps / kavg / 1e12
+        roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK["fp32"], unit="TFLOP/s",
+                        frac=round(achieved / PEAK["fp32"], 4), traffic=measured_traffic(name),
+                        kernel="vdp_chain_kernel", kernel_ms=round(kavg * 1e3, 4), flops_per_dof_step=fpd,
+                        impl_flops_per_dof_step=IMPL_VDP_CHAIN_FLOPS,
+                        impl_frac=round(IMPL_VDP_CHAIN_FLOPS * dof_steps / kavg / 1e12 / PEAK["fp32"], 4))
     elif spec.get("driven"):
         fpd = ALG_DRIVEN_CHAIN_FLOPS
         achieved = fpd * dof_steps / kavg / 1e12
@@ -372,7 +402,7 @@ def bench_batched(args, name, spec):
         "roofline": roofline,
     }
 
-    if not args.no_plain and not spec.get("driven"):
+    if not args.no_plain and not spec.get("driven") and not spec.get("vdp"):
         pn = min(args.plain_instances, w.batch)
         psteps = args.plain_steps or w.nsteps
         sub = w.subset(np.arange(pn))

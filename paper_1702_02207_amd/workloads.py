@@ -213,6 +213,15 @@ def c3_driven_chain(batch: int = 4096, s: int = 1024, nsteps: int = 10_000, out_
     return w, Excitation(0.05, 1e-5, F.copy(), omega.copy())
 
 
+def c3_vdp_chain(batch: int = 4096, s: int = 1024, nsteps: int = 10_000, out_stride: int = 1000,
+                  mu: float = 20.0):
+    """The C3 chains (same masses, springs, x0 ~ N(0, 1e-2)) with a Van der
+    Pol element on every body, mu = 20: over the run (about 0.36 time units)
+    the elements pump the small initial motion towards their limit cycles.
+    Returns (ChainBatch, mu)."""
+    return c3_spring_chain(batch=batch, s=s, nsteps=nsteps, out_stride=out_stride), mu
+
+
 def c4_driven_dense(batch: int = 8192, s: int = 256, nsteps: int = 10_000, out_stride: int = 1000):
     """The C4 dense system (one operator shared by every instance, same x0)
     with Rayleigh damping alpha = 0.02, beta = 1e-3, forces F ~ N(0, 1) per
