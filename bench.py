@@ -87,9 +87,9 @@ IMPL_DRIVEN_CHAIN_FLOPS = 66
 ALG_VDP_CHAIN_FLOPS = 61
 # the register kernel's form (FMA = 2): B x with split coefficients (8), three
 # high-coefficient stencils of the offsets (4 each), the four slopes with
-# their offsets and running sums (5 + 1, 13, 13, 11), the stage inputs (2)
-# and the two Kahan updates (13)
-IMPL_VDP_CHAIN_FLOPS = 78
+# their offsets and the low parts' sums (11, 14, 14, 10) and the two Kahan
+# updates (10)
+IMPL_VDP_CHAIN_FLOPS = 79
 
 WORKLOADS = {
     "c1": dict(kind="chain", method="rk4", prec="f64",

@@ -161,22 +161,32 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
     if (stride > 0 && untouched && n % stride == 0) write_frame(n / stride, true);
     const std::true_type split{};
     const std::false_type hi_only{};
-    while (n < nend) {
-        T xe[DPL], we[DPL], R[DPL], d[DPL], Bd[DPL], kc[DPL], sx[DPL], sw[DPL];
+    // FP32: each step ends with both pairs renormalised (|lo| at most half an
+    // ulp of hi), so hi alone is the pair rounded to T: the stages read x and
+    // w, and during the step the low parts collect the increments, x's the
+    // small part of dx (starting from both low parts), w's dw.
+    if constexpr (COMP) {
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            xe[j] = COMP ? x[j] + xl[j] : x[j];
-            we[j] = COMP ? w[j] + wl[j] : w[j];
+            T t = x[j] + xl[j];
+            xl[j] = xl[j] - (t - x[j]);
+            x[j] = t;
+            t = w[j] + wl[j];
+            wl[j] = wl[j] - (t - w[j]);
+            w[j] = t;
         }
-        bop(split, xe, R);   // B x
+    }
+    while (n < nend) {
+        T R[DPL], d[DPL], Bd[DPL], kc[DPL];
+        bop(split, x, R);   // B x
         // stage 1 at (x, w)
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const T k = fma_t(gm[j] * fma_t(-xe[j], xe[j], T(1)), we[j], -R[j]);
+            const T k = fma_t(gm[j] * fma_t(-x[j], x[j], T(1)), w[j], -R[j]);
             kc[j] = k;
-            sx[j] = k;
-            sw[j] = k;
-            d[j] = T(0.5) * we[j];   // d_2
+            xl[j] = fma_t(T(1.0 / 6.0), k, xl[j] + wl[j]);
+            wl[j] = fma_t(T(1.0 / 6.0), k, wl[j]);
+            d[j] = T(0.5) * w[j];   // d_2
         }
         // stages 2 and 3 at (x + d_k, w + k_{k-1}/2)
 #pragma unroll
@@ -184,41 +194,40 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
             bop(hi_only, d, Bd);
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                const T xt = xe[j] + d[j];
-                const T wt = fma_t(T(0.5), kc[j], we[j]);
+                const T xt = x[j] + d[j];
+                const T wt = fma_t(T(0.5), kc[j], w[j]);
                 const T k = fma_t(gm[j] * fma_t(-xt, xt, T(1)), wt, -(R[j] + Bd[j]));
                 // d_3 = w/2 + k_1/4 = wt/2 (stage 2); d_4 = w + k_2/2 = wt (stage 3)
                 d[j] = st == 2 ? T(0.5) * wt : wt;
                 kc[j] = k;
-                sx[j] += k;
-                sw[j] = fma_t(T(2), k, sw[j]);
+                xl[j] = fma_t(T(1.0 / 6.0), k, xl[j]);
+                wl[j] = fma_t(T(1.0 / 3.0), k, wl[j]);
             }
         }
         // stage 4 at (x + d_4, w + k_3)
         bop(hi_only, d, Bd);
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const T xt = xe[j] + d[j];
-            const T wt = we[j] + kc[j];
+            const T xt = x[j] + d[j];
+            const T wt = w[j] + kc[j];
             const T k = fma_t(gm[j] * fma_t(-xt, xt, T(1)), wt, -(R[j] + Bd[j]));
-            const T ax = sx[j] * T(1.0 / 6.0);   // x increment beyond w
-            const T aw = (sw[j] + k) * T(1.0 / 6.0);
+            wl[j] = fma_t(T(1.0 / 6.0), k, wl[j]);
             if constexpr (COMP) {
-                // x += w (exact error kept) + the small parts; then w
+                // x += w (its exact error kept) + the collected part; renormalise both pairs
                 T t = x[j] + w[j];
-                const T e = w[j] - (t - x[j]);
+                xl[j] += w[j] - (t - x[j]);
                 x[j] = t;
-                xl[j] += e + (wl[j] + ax);
                 t = x[j] + xl[j];
                 xl[j] = xl[j] - (t - x[j]);
                 x[j] = t;
-                wl[j] += aw;
                 t = w[j] + wl[j];
                 wl[j] = wl[j] - (t - w[j]);
                 w[j] = t;
             } else {
-                x[j] += we[j] + ax;
-                w[j] += aw;
+                x[j] += w[j] + xl[j];
+                w[j] += wl[j];
+                xl[j] = T(0);
+                wl[j] = T(0);
             }
         }
         ++n;
@@ -249,10 +258,10 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
     if (!ok && a.nonfinite) atomicOr(a.nonfinite, 1);
 }
 
-// Two waves per SIMD, one for 16 DOFs per lane (the stage values of 16 DOFs
+// Two waves per SIMD; one for FP64 with 16 DOFs per lane (its stage values
 // do not fit half the registers).
 template <typename T, int DPL, int LPI>
-__global__ void __launch_bounds__(kThreads, DPL == 16 ? 1 : 2) vdp_chain_kernel(VdpLaunch<T> a) {
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 2) vdp_chain_kernel(VdpLaunch<T> a) {
     vdp_chain_run<T, DPL, LPI>(a, (int64_t)blockIdx.x * kThreads + threadIdx.x);
 }
 
