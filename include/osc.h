@@ -311,7 +311,8 @@ osc_status osc_set_config(osc_sys *sys, osc_config key, int64_t value);
  * file, the choice is appended to it, and osc_create applies the cached
  * choice for the same kind, method, precision, s, batch size class and GPU.
  * Synchronous.  Chain layouts give bitwise-identical results; dense kernels
- * agree within the FP32 tolerance.
+ * agree within the FP32 tolerance.  OSC_ENOTSUP for handles with damping,
+ * a force or Van der Pol elements (their kernels take fixed layouts).
  */
 osc_status osc_autotune(osc_sys *sys, const void *x0, const void *v0, int64_t probe_steps, int64_t *chosen);
 

@@ -83,6 +83,11 @@ extern "C" osc_status osc_autotune(osc_sys *s, const void *x0, const void *v0, i
                                    int64_t *chosen) {
     if (!s || !x0 || !v0) return fail(OSC_EINVAL, "handle, x0 and v0 must be non-NULL");
     if (probe_steps < 1) return fail(OSC_EINVAL, "probe_steps must be >= 1");
+    // their kernels choose their own layouts, and a time measured on them
+    // must not enter the cache under the free system's key
+    if (s->driven || s->vdp_mu > 0.0)
+        return fail(OSC_ENOTSUP, "osc_autotune tunes the free integrators; damped, driven and Van der Pol "
+                                 "handles take fixed layouts");
     if (s->batch == 0) return OSC_OK;
     std::vector<int64_t> cands;
     if (s->kind == OSC_CHAIN) {

@@ -147,7 +147,8 @@ def test_vdp_rejects_what_it_does_not_cover():
         for call in (lambda: sysm.set_excitation(0.1, 0.0),
                      lambda: sysm.set_config(osc.CFG_PROPAGATOR, 1),
                      lambda: sysm.propagator(3),
-                     lambda: sysm.integrate_plain(X0, X0, 10)):
+                     lambda: sysm.integrate_plain(X0, X0, 10),
+                     lambda: sysm.autotune(X0, X0, probe_steps=5)):
             with pytest.raises(osc.OscError) as e:
                 call()
             assert e.value.status == osc.OSC_ENOTSUP
@@ -155,6 +156,9 @@ def test_vdp_rejects_what_it_does_not_cover():
         sysm.set_excitation(0.1, 0.0)
         with pytest.raises(osc.OscError) as e:
             sysm.set_van_der_pol(mu)
+        assert e.value.status == osc.OSC_ENOTSUP
+        with pytest.raises(osc.OscError) as e:      # damped: fixed layouts, nothing to tune
+            sysm.autotune(X0, X0, probe_steps=5)
         assert e.value.status == osc.OSC_ENOTSUP
     finally:
         sysm.close()
