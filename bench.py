@@ -167,7 +167,7 @@ def make_workload(name):
 
 # kernel sources that decide the dominant kernel of each workload family
 TRAFFIC_SOURCES = {"chain": ("chain.hip", "chain_run.h", "osc_internal.h"), "dense": ("dense_mfma.hip", "osc_internal.h"),
-                   "driven": ("driven.hip", "driven_run.h", "osc_internal.h"), "vdp": ("vdp.hip", "osc_internal.h")}
+                   "driven": ("driven.hip", "driven_run.h", "osc_internal.h"), "vdp": ("vdp.hip", "vdp_run.h", "osc_internal.h")}
 
 
 def src_hash(workload):

@@ -30,8 +30,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # instance in registers and have DPL independent DOFs at every stage; the
 # register-pressure-first default schedule chains them one DOF at a time
 # (back-to-back dependent instructions), the ILP-first schedule interleaves
-# them.  The resident real-time kernels run the same per-lane integrator.
-PER_FILE = {name: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"] for name in ("chain.hip", "resident.hip")}
+# them.  The resident real-time kernels run the same per-lane integrator, and
+# the FP32 Van der Pol chains (vdp.hip; FP64 in vdp_f64.hip keeps the default:
+# with the ILP-first schedule its 16-DOF layout spills) have the same shape.
+PER_FILE = {name: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"] for name in ("chain.hip", "resident.hip", "vdp.hip")}
 
 
 def _compile(src: str, verbose: bool) -> str:
