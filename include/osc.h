@@ -215,15 +215,15 @@ osc_status osc_set_excitation(osc_sys *sys, double alpha, double beta, const dou
  * the spring chain of eq. (2) with each body pumped while |x_i| < 1 and
  * damped beyond.  mu >= 0, finite, the same for every instance; mu = 0 makes
  * the handle linear again.  Afterwards osc_integrate (and osc_integrate_static
- * and the launch-per-tick real-time stepper) run classic RK4 in stage form on
- * the first-order system of section 3, in registers.  The linear stability
+ * and both real-time steppers) run classic RK4 in stage form on the
+ * first-order system of section 3, in registers.  The linear stability
  * check of osc_create still applies; the nonlinear term is not bounded by it
  * (a step too long for the amplitude reached shows as OSC_ENONFINITE from
  * osc_sync).  osc_energy returns 1/2 v^T M v + 1/2 x^T K x (not conserved).
  * OSC_EINVAL for a negative or non-finite mu; OSC_ENOTSUP for dense handles,
  * Verlet handles, s > 1024, a handle with osc_set_excitation damping or force,
- * or a propagator mode.  The plain baseline, osc_propagator and the resident
- * real-time stepper return OSC_ENOTSUP while mu > 0.  Synchronous, host only.
+ * or a propagator mode.  The plain baseline, osc_propagator and osc_autotune
+ * return OSC_ENOTSUP while mu > 0.  Synchronous, host only.
  */
 osc_status osc_set_van_der_pol(osc_sys *sys, double mu);
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "osc_internal.h"
+#include "vdp.h"
 
 // Device scratch of the allocation-free entry point (osc_integrate_static):
 // each device that runs the library holds its own copy from the library's
@@ -1082,7 +1083,6 @@ osc_status sys_rt_supported(const osc_sys *s) {
 
 osc_status sys_rt_resident_supported(const osc_sys *s) {
     if (s->kind != OSC_CHAIN) return fail(OSC_ENOTSUP, "resident real-time stepping takes chains only");
-    if (s->vdp_mu > 0.0) return fail(OSC_ENOTSUP, "resident real-time stepping takes linear chains");
     if (s->driven && (s->s > 1024 || s->dense_kernel == 1))
         return fail(OSC_ENOTSUP, "resident real-time stepping of damped or driven chains takes the register "
                                  "kernels (s <= 1024)");
@@ -1103,6 +1103,20 @@ osc_status rt_resident(osc_sys *s, const void *x0, const void *v0, const Residen
     r.vf = static_cast<T *>(spec.vf);
     r.xo = static_cast<T *>(spec.xo);
     r.vo = static_cast<T *>(spec.vo);
+    if (s->vdp_mu > 0.0) {
+        VdpLaunch<T> d{};
+        d.batch = s->batch;
+        d.s = s->s;
+        d.c = coef_of<T>(s);
+        d.m = s->m;
+        d.mu = s->vdp_mu;
+        d.x0 = static_cast<const T *>(x0);
+        d.v0 = static_cast<const T *>(v0);
+        d.state = static_cast<T *>(state_buf(s));
+        d.nonfinite = s->flag;
+        *blocks = vdp_resident_blocks<T>(d);
+        return vdp_resident_launch<T>(d, r, s->stream);
+    }
     if (s->driven) {
         DrivenLaunch<T> d{};
         d.kind = OSC_CHAIN;

@@ -1,5 +1,5 @@
-// Resident real-time stepping of chains (free, or damped and driven in the
-// register layouts): one kernel stays on the device for a whole periodic run and advances the state one tick (steps_per_tick steps)
+// Resident real-time stepping of chains (free, damped and driven, or Van der
+// Pol, in the register layouts): one kernel stays on the device for a whole periodic run and advances the state one tick (steps_per_tick steps)
 // each time the host raises a release counter in host-mapped memory, instead
 // of one launch per tick.  The host writes the counter at each release time
 // and polls a completion count that the kernel raises once per workgroup and
@@ -23,6 +23,8 @@
 
 #include "chain_run.h"
 #include "driven_run.h"
+#include "vdp.h"
+#include "vdp_run.h"
 
 namespace osc {
 namespace {
@@ -116,6 +118,40 @@ __global__ void __launch_bounds__(kResidentThreads, (sizeof(T) == 8 && DPL == 16
         __hip_atomic_store(&r.ctl->exit_reason, reason, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+template <typename T, int DPL, int LPI>
+__global__ void __launch_bounds__(kResidentThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 2)
+    vdp_resident_kernel(VdpLaunch<T> a, ResidentRun<T> r) {
+    __shared__ int go;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t plane = (size_t)a.batch * a.s;
+    int reason = kRtExitTicks;
+    for (int64_t i = 0; i < r.nticks; ++i) {
+        if (threadIdx.x == 0) go = wait_release(r.ctl, r.first_release + i + 1, r.idle_ticks);
+        __syncthreads();
+        const int gv = go;
+        __syncthreads();
+        if (gv != 1) {
+            reason = gv == 0 ? kRtExitStop : kRtExitIdle;
+            break;
+        }
+        VdpLaunch<T> t = a;
+        t.n0 = r.n_start + i * r.k;
+        t.nsteps = r.k;
+        t.out_stride = 0;
+        t.load_mode = t.n0 == 0 ? LOAD_USER : LOAD_STATE;
+        t.store_mode = STORE_STATE | STORE_USER;
+        t.xe = r.xf ? r.xf + (size_t)i * plane : r.xo;
+        t.ve = r.vf ? r.vf + (size_t)i * plane : r.vo;
+        vdp_chain_run<T, DPL, LPI>(t, g);
+        __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&r.ctl->done, (uint64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (threadIdx.x == 0 && reason != kRtExitTicks)
+        __hip_atomic_store(&r.ctl->exit_reason, reason, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Every workgroup must be resident at once: one that waits for a free CU
 // would only start when the others end.
 osc_status check_resident(const void *f, int64_t blocks, int bs) {
@@ -182,6 +218,17 @@ osc_status launch_method(const ChainLaunch<T> &a, ChainConfig cfg, const Residen
 
 }  // namespace
 
+template <typename T, int DPL, int LPI>
+osc_status launch_vdp_layout(const VdpLaunch<T> &a, const ResidentRun<T> &r, hipStream_t st) {
+    void (*f)(VdpLaunch<T>, ResidentRun<T>) = &vdp_resident_kernel<T, DPL, LPI>;
+    const int64_t blocks = (a.batch * LPI + kResidentThreads - 1) / kResidentThreads;
+    osc_status e = check_resident(reinterpret_cast<const void *>(f), blocks, kResidentThreads);
+    if (e) return e;
+    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(kResidentThreads), 0, st, a, r);
+    OSC_HIP(hipGetLastError());
+    return OSC_OK;
+}
+
 template <typename T>
 int64_t chain_resident_blocks(const ChainLaunch<T> &a, ChainConfig cfg) {
     const int bs = cfg.lpi == 128 ? 128 : kResidentThreads;
@@ -219,6 +266,33 @@ osc_status driven_resident_launch(const DrivenLaunch<T> &a, const ResidentRun<T>
     return fail(OSC_ENOTSUP, "resident stepping of damped or driven chains takes s <= 1024");
 }
 
+template <typename T>
+int64_t vdp_resident_blocks(const VdpLaunch<T> &a) {
+    int dpl = 0, lpi = 0;
+    if (!driven_regs_layout(a.s, &dpl, &lpi)) return 0;   // the same layouts
+    return (a.batch * lpi + kResidentThreads - 1) / kResidentThreads;
+}
+
+template <typename T>
+osc_status vdp_resident_launch(const VdpLaunch<T> &a, const ResidentRun<T> &r, hipStream_t st) {
+    if (a.batch == 0) return fail(OSC_EINVAL, "resident stepping needs at least one instance");
+    const int s = a.s;
+    if (s <= 1) return launch_vdp_layout<T, 1, 1>(a, r, st);
+    if (s <= 2) return launch_vdp_layout<T, 2, 1>(a, r, st);
+    if (s <= 4) return launch_vdp_layout<T, 4, 1>(a, r, st);
+    if (s <= 8) return launch_vdp_layout<T, 8, 1>(a, r, st);
+    if (s <= 64) return launch_vdp_layout<T, 1, 64>(a, r, st);
+    if (s <= 128) return launch_vdp_layout<T, 2, 64>(a, r, st);
+    if (s <= 256) return launch_vdp_layout<T, 4, 64>(a, r, st);
+    if (s <= 512) return launch_vdp_layout<T, 8, 64>(a, r, st);
+    if (s <= 1024) return launch_vdp_layout<T, 16, 64>(a, r, st);
+    return fail(OSC_ENOTSUP, "resident stepping of Van der Pol chains takes s <= 1024");
+}
+
+template int64_t vdp_resident_blocks<float>(const VdpLaunch<float> &);
+template int64_t vdp_resident_blocks<double>(const VdpLaunch<double> &);
+template osc_status vdp_resident_launch<float>(const VdpLaunch<float> &, const ResidentRun<float> &, hipStream_t);
+template osc_status vdp_resident_launch<double>(const VdpLaunch<double> &, const ResidentRun<double> &, hipStream_t);
 template int64_t driven_resident_blocks<float>(const DrivenLaunch<float> &);
 template int64_t driven_resident_blocks<double>(const DrivenLaunch<double> &);
 template osc_status driven_resident_launch<float>(const DrivenLaunch<float> &, const ResidentRun<float> &,

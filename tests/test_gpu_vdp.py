@@ -90,31 +90,34 @@ def test_vdp_chunked_and_static_runs_are_bitwise_one_launch(prec):
         np.testing.assert_array_equal(a, c)
 
 
-def test_vdp_real_time_ticks_are_the_frames_of_one_integration():
-    """The launch-per-tick real-time stepper on a Van der Pol pair (the two
-    coupled oscillators of the paper's section 1, FP64): the states after the
-    ticks equal the frames of one osc_integrate call bit for bit."""
+@pytest.mark.parametrize("prec,s,batch", [("f64", 2, 1), ("f32", 2, 3), ("f32", 300, 2), ("f64", 700, 1)])
+def test_vdp_real_time_ticks_are_the_frames_of_one_integration(prec, s, batch):
+    """Both real-time steppers on Van der Pol chains (the pair is the two
+    coupled oscillators of the paper's section 1): the states after the ticks
+    of the launch-per-tick loop and of the resident kernel equal the frames of
+    one osc_integrate call bit for bit."""
     import torch
-    m, k, dt, mu, x0, v0 = _vdp(960, 1, 2, 400, 4)
-    sysm = osc.System("chain", "rk4", "f64", m, k, dt).create()
+    dtype = torch.float32 if prec == "f32" else torch.float64
+    m, k, dt, mu, x0, v0 = _vdp(960 + s, batch, s, 400, 4)
+    sysm = osc.System("chain", "rk4", prec, m, k, dt).create()
     try:
         sysm.set_van_der_pol(mu)
-        X0, V0 = to_dev(x0, torch.float64), to_dev(v0, torch.float64)
+        X0, V0 = to_dev(x0, dtype), to_dev(v0, dtype)
         xf, vf, _, _ = sysm.integrate(X0, V0, 400, 4)
         sysm.sync()
         ref_x, ref_v = xf[1:].cpu().numpy(), vf[1:].cpu().numpy()
         with osc.Realtime(sysm, X0, V0, 4) as rt:
             tx, tv, lat, stats = rt.run(100e-6, 100)
             tx, tv = tx.cpu().numpy(), tv.cpu().numpy()
-        with pytest.raises(osc.OscError) as e:
-            with osc.Realtime(sysm, X0, V0, 4) as rt:
-                rt.run_resident(100e-6, 10)
-        assert e.value.status == osc.OSC_ENOTSUP
+        with osc.Realtime(sysm, X0, V0, 4) as rt:
+            rx, rv, rlat, rstats = rt.run_resident(100e-6, 100)
+            rx, rv = rx.cpu().numpy(), rv.cpu().numpy()
     finally:
         sysm.close()
-    np.testing.assert_array_equal(tx, ref_x)
-    np.testing.assert_array_equal(tv, ref_v)
-    assert stats["ticks"] == 100
+    for got in ((tx, tv), (rx, rv)):
+        np.testing.assert_array_equal(got[0], ref_x)
+        np.testing.assert_array_equal(got[1], ref_v)
+    assert stats["ticks"] == 100 and rstats["ticks"] == 100
 
 
 def test_vdp_rejects_what_it_does_not_cover():
