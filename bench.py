@@ -544,6 +544,19 @@ def realtime_pass(args):
                                        "p99_latency_s": st["p99_s"], "max_latency_s": st["max_s"],
                                        "jitter_s": st["jitter_s"], "missed": int(st["missed"]),
                                        "gpu_p50_s": st["gpu_p50_s"], "launch_p99_s": st["launch_p99_s"]})
+        # the same pair with a Van der Pol element on each mass (mu = 10): the
+        # nonlinear coupled oscillators of section 1, on the resident kernel
+        sysm.set_van_der_pol(10.0)
+        out["van_der_pol"] = {"workload": "the same pair with a Van der Pol element on each mass, mu = 10",
+                              "periods": []}
+        for period in (20e-6, 100e-6):
+            _log(f"[bench] real-time (resident, Van der Pol): period {period * 1e6:.0f} us, {args.rt_ticks} ticks")
+            with osc.Realtime(sysm, x0, v0, 1) as rt:
+                _, _, _, st = rt.run_resident(period, args.rt_ticks, frames=False)
+            out["van_der_pol"]["periods"].append({"mode": "resident", "period_s": period,
+                                                   "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
+                                                   "max_latency_s": st["max_s"], "jitter_s": st["jitter_s"],
+                                                   "missed": int(st["missed"])})
     finally:
         sysm.close()
     return out
