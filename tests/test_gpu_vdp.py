@@ -34,7 +34,7 @@ def _run(sysm, x0, v0, nsteps, stride, prec, static=False):
     dt = torch.float32 if prec == "f32" else torch.float64
     out = sysm.integrate(to_dev(x0, dt), to_dev(v0, dt), nsteps, stride, static=static)
     sysm.sync()
-    return [t.double().cpu().numpy() for t in out]
+    return [None if t is None else t.double().cpu().numpy() for t in out]
 
 
 def _inputs(x0, v0, prec):
@@ -163,5 +163,29 @@ def test_vdp_rejects_what_it_does_not_cover():
         with pytest.raises(osc.OscError) as e:      # damped: fixed layouts, nothing to tune
             sysm.autotune(X0, X0, probe_steps=5)
         assert e.value.status == osc.OSC_ENOTSUP
+    finally:
+        sysm.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_vdp_step_too_long_for_mu_reports_nonfinite(prec):
+    """The linear stability check of osc_create cannot bound the nonlinear
+    term: with h mu |x|^2 far beyond RK4's region the state overflows, as the
+    oracle's does, and osc_sync reports OSC_ENONFINITE."""
+    m = np.array([[1.0, 1.0]])
+    k = np.array([[1.0, 1.0]])
+    dt = np.array([0.05])
+    x0 = np.array([[2.0, -1.0]])
+    v0 = np.zeros((1, 2))
+    _, _, xe, _ = oracle.chain_vdp(m, k, dt, 100.0, x0, v0, 200, 0, frames=False)
+    assert not np.isfinite(xe).all()
+    sysm = osc.System("chain", "rk4", prec, m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(100.0)
+        with pytest.raises(osc.OscError) as e:
+            _run(sysm, x0, v0, 200, 0, prec)
+        assert e.value.status == osc.OSC_ENONFINITE
+        sysm.set_van_der_pol(1.0)                   # a step that suits mu: finite again
+        _run(sysm, x0, v0, 200, 0, prec)
     finally:
         sysm.close()
