@@ -7,15 +7,18 @@
 // (tau = t/h, w = h v, B = h^2 M^-1 K, g_i = h mu / m_i):
 //     x' = w,   w' = -B x + g (1 - x^2) w.
 // The linear Taylor form of the free chains does not apply (the right-hand
-// side is nonlinear), so the four stages are evaluated in turn.  Stage k's
-// argument is (x + d_k, w + c_k) with the offsets d_2 = w/2,
-// d_3 = w/2 + k_1/4, d_4 = w + k_2/2 (k_j the stages' w-slopes), so that
-//     B (x + d_k) = B x + B d_k:
+// side is nonlinear), so the four stages are evaluated in turn.  With k_j
+// the stages' w-slopes, stage j's argument is (x + d_j, w + c_j) with
+// d_2 = w/2, d_3 = w/2 + k_1/4, d_4 = w + k_2/2 and c_2 = k_1/2,
+// c_3 = k_2/2, c_4 = k_3, so that
+//     B (x + d_j) = B x + B d_j:
 // B x takes the split FP32 coefficients once per step, the small offsets
-// the high parts only.  The increments
+// the high parts only.  The increments are
 //     dx = w + (k_1 + k_2 + k_3)/6,   dw = (k_1 + 2 k_2 + 2 k_3 + k_4)/6
-// (the x-slopes of RK4 are w plus the offsets) go into the compensated
-// state as in the damped, driven kernel (FP64: a plain update).
+// (the x-slopes of RK4 are w plus the offsets).  FP32 keeps x and w as
+// renormalised hi + lo pairs: the stages read the high parts, the low parts
+// collect the increments as they are formed, and x += w keeps its exact
+// rounding error (FP64: a plain update).
 //
 // Layouts: those of the damped, driven register kernel (one lane per chain
 // for s <= 8, one wave per chain beyond, DPP halos, no LDS), s <= 1024.
