@@ -189,3 +189,31 @@ def test_vdp_step_too_long_for_mu_reports_nonfinite(prec):
         _run(sysm, x0, v0, 200, 0, prec)
     finally:
         sysm.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("nsteps,stride", [(0, 10), (0, 0), (7, 100), (100, 100), (1, 0)])
+def test_vdp_degenerate_runs(prec, nsteps, stride):
+    """No step (the caller's state comes back unchanged), a stride beyond the
+    run (frame 0 only), a stride equal to the run and a single step."""
+    m, k, dt, mu, x0, v0 = _vdp(990 + nsteps, 3, 37, nsteps, stride)
+    v0 = np.random.default_rng(5).normal(0.0, 1.0, x0.shape)
+    sysm = osc.System("chain", "rk4", prec, m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(mu)
+        xf, vf, xe, ve = _run(sysm, x0, v0, nsteps, stride, prec)
+    finally:
+        sysm.close()
+    x0r, v0r = _inputs(x0, v0, prec)
+    rx, rv, rxe, rve = oracle.chain_vdp(m, k, dt, mu, x0r, v0r, nsteps, stride)
+    if nsteps == 0:
+        np.testing.assert_array_equal(xe, x0r)
+        np.testing.assert_array_equal(ve, v0r)
+    if rx is not None:
+        assert xf.shape == rx.shape
+        np.testing.assert_array_equal(xf[0], x0r)
+        assert max(oracle.rel_traj_err(xf, rx).max(), oracle.rel_traj_err(vf, rv).max()) < TOL[prec]
+    else:
+        assert xf is None and vf is None
+    scale = np.maximum(np.abs(rxe).max(axis=1), 1e-300)
+    assert (np.abs(xe - rxe).max(axis=1) / scale).max() < TOL[prec]
