@@ -58,7 +58,7 @@ def _load():
     lib.oracle_dense_driven.argtypes = [i64, i32, i32, d, d, d, dbl, dbl, d, d, d, d, i64, i64, d, d, d, d]
     lib.oracle_dopri_driven.argtypes = [i32, i32, d, d, dbl, dbl, d, dbl, d, d, dbl, i32, dbl, dbl, d, d,
                                         ctypes.POINTER(ctypes.c_int64)]
-    lib.oracle_chain_vdp.argtypes = [i64, i32, d, d, d, dbl, d, d, i64, i64, d, d, d, d]
+    lib.oracle_chain_vdp.argtypes = [i64, i32, d, d, d, dbl, d, d, d, d, i64, i64, d, d, d, d]
     lib.oracle_dopri_vdp.argtypes = [i32, d, d, dbl, d, d, dbl, i32, dbl, dbl, d, d,
                                      ctypes.POINTER(ctypes.c_int64)]
     for f in ("oracle_chain_vdp", "oracle_dopri_vdp", "oracle_chain_driven", "oracle_dense_driven", "oracle_dopri_driven", "oracle_propagator", "oracle_chain", "oracle_dense", "oracle_form_a", "oracle_energy_chain",
@@ -251,18 +251,20 @@ def dopri_driven(kind, a, b, alpha, beta, F, omega, x0, v0, t_end, nout, rtol=1e
     return xo, vo, int(stats[0]), int(stats[1])
 
 
-def chain_vdp(m, k, dt, mu, x0, v0, nsteps, stride, frames=True):
+def chain_vdp(m, k, dt, mu, x0, v0, nsteps, stride, frames=True, F=None, omega=None):
     """Classic RK4 for coupled Van der Pol chains: m_i x_i'' - mu (1 - x_i^2)
-    x_i' + (K x)_i = 0 with the chain's K.  Returns (x_frames, v_frames,
-    x_end, v_end)."""
+    x_i' + (K x)_i = F_i cos(omega t) with the chain's K (F [batch, s] or
+    None, omega [batch] or a scalar).  Returns (x_frames, v_frames, x_end,
+    v_end)."""
     lib = _load()
     m, k, dt, x0, v0 = map(_f64, (m, k, dt, x0, v0))
     batch, s = x0.shape
+    F, omega = _driven_force(F, omega, batch)
     nf = _nframes(nsteps, stride) if frames else 0
     xf = np.empty((nf, batch, s)) if nf else None
     vf = np.empty((nf, batch, s)) if nf else None
     xe, ve = np.empty((batch, s)), np.empty((batch, s))
-    st = lib.oracle_chain_vdp(batch, s, _p(m), _p(k), _p(dt), float(mu), _p(x0), _p(v0), int(nsteps),
+    st = lib.oracle_chain_vdp(batch, s, _p(m), _p(k), _p(dt), float(mu), _p(F), _p(omega), _p(x0), _p(v0), int(nsteps),
                               int(stride) if nf else 0, _p(xf), _p(vf), _p(xe), _p(ve))
     _check(st, "oracle_chain_vdp")
     return xf, vf, xe, ve

@@ -585,34 +585,40 @@ int oracle_chain_driven(int64_t batch, int s, const double *m, const double *k, 
 
 /* Coupled Van der Pol chains (the nonlinear oscillators section 1 names as the
  * standard model of the field): the chain of eq. (2) with a Van der Pol
- * element on every body,
- *     m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = 0,
- * by classic RK4 on the first-order system (stages as above).  mu = 0 gives
- * the free chain, by the same operations as the damped, driven integrator. */
+ * element on every body, optionally driven by a harmonic force,
+ *     m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = F_i cos(Omega t),
+ * by classic RK4 on the first-order system (stages as above; F [batch][s] or
+ * NULL, omega [batch]).  mu = 0 gives the free (or driven) chain by the same
+ * operations as the damped, driven integrator. */
 int oracle_chain_vdp(int64_t batch, int s, const double *m, const double *k, const double *dt, double mu,
-                     const double *x0, const double *v0, int64_t nsteps, int64_t stride, double *xf,
-                     double *vf, double *xe, double *ve) {
+                     const double *F, const double *omega, const double *x0, const double *v0, int64_t nsteps,
+                     int64_t stride, double *xf, double *vf, double *xe, double *ve) {
     int st = check_common(ORC_RK4, batch, s, dt, x0, v0, nsteps, stride);
     if (st) return st;
-    if (batch > 0 && (!m || !k)) return ORC_EINVAL;
+    if (batch > 0 && (!m || !k || (F && !omega))) return ORC_EINVAL;
     if (!(mu >= 0.0) || !isfinite(mu)) return ORC_EINVAL;
     int fail = 0;
 #pragma omp parallel
     {
         double *work = (double *)malloc(sizeof(double) * ORC_DRIVEN_WORK_PER_DOF * (size_t)s);
-        if (!work) {
+        double *f = (double *)malloc(sizeof(double) * s);
+        if (!work || !f) {
 #pragma omp atomic write
             fail = ORC_ENOMEM;
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int64_t b = 0; b < batch; ++b) {
-                drive_t d = {0.0, 0.0, 0.0, NULL, mu};
-                rhs_t r = {0, s, m + (size_t)b * s, k + (size_t)b * s, NULL};
+                const double *mb = m + (size_t)b * s;
+                if (F)
+                    for (int i = 0; i < s; ++i) f[i] = F[(size_t)b * s + i] / mb[i];
+                drive_t d = {0.0, 0.0, F ? omega[b] : 0.0, F ? f : NULL, mu};
+                rhs_t r = {0, s, mb, k + (size_t)b * s, NULL};
                 integrate_driven_one(&r, &d, dt[b], x0 + (size_t)b * s, v0 + (size_t)b * s, nsteps, stride,
                                      batch, b, xf, vf, xe, ve, work);
             }
         }
         free(work);
+        free(f);
     }
     return fail;
 }

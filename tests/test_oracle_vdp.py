@@ -63,6 +63,35 @@ def test_energy_balance_along_the_trajectory(mu):
     assert abs(dE) > 1e-3 * E.max()
 
 
+def test_forced_vdp_reduces_to_the_driven_chain_and_balances_energy():
+    """With a harmonic force: at mu = 0 the operations of the driven chain
+    (no damping) bit for bit; at mu > 0 the energy changes by the elements'
+    power plus the force's, mu sum (1 - x_i^2) v_i^2 + sum F_i cos(Omega t) v_i,
+    integrated over the frames by Simpson's rule."""
+    rng = np.random.default_rng(8)
+    s, h, n = 3, 2e-3, 5000
+    m = rng.uniform(0.5, 2.0, (1, s))
+    k = rng.uniform(0.5, 2.0, (1, s))
+    x0 = rng.normal(0.0, 1.0, (1, s))
+    v0 = rng.normal(0.0, 1.0, (1, s))
+    F = rng.normal(0.0, 2.0, (1, s))
+    W = np.array([1.3])
+    got = oracle.chain_vdp(m, k, np.array([h]), 0.0, x0, v0, 400, 100, F=F, omega=W)
+    drv = oracle.chain_driven(m, k, np.array([h]), 0.0, 0.0, F, W, x0, v0, 400, 100)
+    for a, b in zip(got, drv):
+        np.testing.assert_array_equal(a, b)
+    mu = 0.7
+    xf, vf, _, _ = oracle.chain_vdp(m, k, np.array([h]), mu, x0, v0, n, 1, F=F, omega=W)
+    x, v = xf[:, 0], vf[:, 0]
+    t = np.arange(n + 1) * h
+    E = oracle.energy_chain(np.repeat(m, n + 1, 0), np.repeat(k, n + 1, 0), x, v)
+    P = mu * ((1.0 - x * x) * v * v).sum(axis=1) + np.cos(W[0] * t) * (F * v).sum(axis=1)
+    work = h / 3.0 * (P[0] + P[-1] + 4.0 * P[1:-1:2].sum() + 2.0 * P[2:-1:2].sum())
+    dE = E[-1] - E[0]
+    print(f"forced: dE {dE:.12e}, integrated power {work:.12e}")
+    assert abs(dE - work) < 1e-8 * max(abs(dE), E.max())
+
+
 def test_small_mu_amplitude_follows_averaging():
     """One body (m = k = 1), mu = 0.05, from amplitude 0.5: first-order
     averaging gives a(t) = 2 / sqrt(1 + (4/a0^2 - 1) exp(-mu t)); the
@@ -146,8 +175,8 @@ def test_pins_catch_planted_vdp_mistakes(orig, mut, tmp_path):
                     "-o", str(lib), str(mpath), "-lm"], check=True)
     L = ctypes.CDLL(str(lib))
     d = ctypes.POINTER(ctypes.c_double)
-    L.oracle_chain_vdp.argtypes = [ctypes.c_int64, ctypes.c_int, d, d, d, ctypes.c_double, d, d, ctypes.c_int64,
-                                   ctypes.c_int64, d, d, d, d]
+    L.oracle_chain_vdp.argtypes = [ctypes.c_int64, ctypes.c_int, d, d, d, ctypes.c_double, d, d, d, d,
+                                   ctypes.c_int64, ctypes.c_int64, d, d, d, d]
     rng = np.random.default_rng(7)
     s, h, n, mu = 3, 2e-3, 5000, 0.3
     m = np.ascontiguousarray(rng.uniform(0.5, 2.0, (1, s)))
@@ -158,7 +187,8 @@ def test_pins_catch_planted_vdp_mistakes(orig, mut, tmp_path):
     xf, vf = np.empty((n + 1, 1, s)), np.empty((n + 1, 1, s))
     xe, ve = np.empty((1, s)), np.empty((1, s))
     p = lambda a: a.ctypes.data_as(d)
-    assert L.oracle_chain_vdp(1, s, p(m), p(k), p(hh), mu, p(x0), p(v0), n, 1, p(xf), p(vf), p(xe), p(ve)) == 0
+    assert L.oracle_chain_vdp(1, s, p(m), p(k), p(hh), mu, None, None, p(x0), p(v0), n, 1, p(xf), p(vf), p(xe),
+                              p(ve)) == 0
     x, v = xf[:, 0], vf[:, 0]
     E = oracle.energy_chain(np.repeat(m, n + 1, 0), np.repeat(k, n + 1, 0), x, v)
     P = mu * ((1.0 - x * x) * v * v).sum(axis=1)
