@@ -200,7 +200,8 @@ osc_status osc_shadow_energy(osc_sys *sys, const void *x, const void *v, double 
  * osc_integrate_plain and the propagator modes return OSC_ENOTSUP; osc_energy
  * still returns 1/2 v^T M v + 1/2 x^T K x (no longer conserved).
  * OSC_ENOTSUP for a Verlet handle (the velocity-dependent force would make the
- * scheme implicit).  OSC_EUNSTABLE when dt * max(omega_max, alpha + beta
+ * scheme implicit), and for damping on a Van der Pol chain (osc_set_van_der_pol;
+ * a force alone drives it).  OSC_EUNSTABLE when dt * max(omega_max, alpha + beta
  * omega_max^2) exceeds 2.5: every mode's |lambda| is at most that, and RK4's
  * stability region holds the left half-disk of radius 2.6156.  Synchronous.
  */
@@ -220,9 +221,13 @@ osc_status osc_set_excitation(osc_sys *sys, double alpha, double beta, const dou
  * check of osc_create still applies; the nonlinear term is not bounded by it
  * (a step too long for the amplitude reached shows as OSC_ENONFINITE from
  * osc_sync).  osc_energy returns 1/2 v^T M v + 1/2 x^T K x (not conserved).
+ * A force set by osc_set_excitation (alpha = beta = 0) drives the Van der Pol
+ * chain: m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = F_i cos(Omega t), the
+ * forced Van der Pol oscillator, with the force's phase as in the damped,
+ * driven integrator.
  * OSC_EINVAL for a negative or non-finite mu; OSC_ENOTSUP for dense handles,
- * Verlet handles, s > 1024, a handle with osc_set_excitation damping or force,
- * or a propagator mode.  The plain baseline, osc_propagator and osc_autotune
+ * Verlet handles, s > 1024, a handle with Rayleigh damping, or a propagator
+ * mode.  The plain baseline, osc_propagator and osc_autotune
  * return OSC_ENOTSUP while mu > 0.  Synchronous, host only.
  */
 osc_status osc_set_van_der_pol(osc_sys *sys, double mu);

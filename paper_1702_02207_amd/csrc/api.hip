@@ -661,6 +661,8 @@ osc_status integrate_vdp(osc_sys *s, const void *x0, const void *v0, int64_t nst
     a.c = coef_of<T>(s);
     a.m = s->m;
     a.mu = s->vdp_mu;
+    a.f = s->force;
+    a.omega = s->omega;
     a.x0 = static_cast<const T *>(x0);
     a.v0 = static_cast<const T *>(v0);
     a.out_stride = out_stride;
@@ -962,8 +964,8 @@ osc_status osc_set_excitation(osc_sys *s, double alpha, double beta, const doubl
     const bool on = alpha != 0.0 || beta != 0.0 || F != nullptr;
     if (on && s->method != OSC_RK4)
         return fail(OSC_ENOTSUP, "damped / driven systems are integrated by RK4 only");
-    if (on && s->vdp_mu > 0.0)
-        return fail(OSC_ENOTSUP, "a handle is either damped / driven or a Van der Pol chain, not both");
+    if (s->vdp_mu > 0.0 && (alpha != 0.0 || beta != 0.0))
+        return fail(OSC_ENOTSUP, "a Van der Pol chain takes a force but no Rayleigh damping");
     const hipStream_t st = s->stream;
     const int64_t nh = s->kind == OSC_CHAIN ? s->batch : s->nsys;
     if ((alpha != 0.0 || beta != 0.0) && nh > 0) {
@@ -1022,7 +1024,8 @@ osc_status osc_set_van_der_pol(osc_sys *s, double mu) {
         if (s->kind != OSC_CHAIN) return fail(OSC_ENOTSUP, "Van der Pol elements are on chains only");
         if (s->method != OSC_RK4) return fail(OSC_ENOTSUP, "Van der Pol chains are integrated by RK4 only");
         if (s->s > 1024) return fail(OSC_ENOTSUP, "Van der Pol chains take s <= 1024");
-        if (s->driven) return fail(OSC_ENOTSUP, "a handle is either damped / driven or a Van der Pol chain, not both");
+        if (s->alpha != 0.0 || s->beta != 0.0)
+            return fail(OSC_ENOTSUP, "a Van der Pol chain takes a force but no Rayleigh damping");
         if (s->propagator) return fail(OSC_ENOTSUP, "the propagator modes take linear systems, not Van der Pol chains");
     }
     s->vdp_mu = mu;
@@ -1110,6 +1113,8 @@ osc_status rt_resident(osc_sys *s, const void *x0, const void *v0, const Residen
         d.c = coef_of<T>(s);
         d.m = s->m;
         d.mu = s->vdp_mu;
+        d.f = s->force;
+        d.omega = s->omega;
         d.x0 = static_cast<const T *>(x0);
         d.v0 = static_cast<const T *>(v0);
         d.state = static_cast<T *>(state_buf(s));

@@ -425,7 +425,8 @@ osc_status chain_force(int64_t n, const double *F, const double *m, double *f, h
 
 // ---------------------------------------------------------------------------
 // coupled Van der Pol chains (vdp.hip): m_i x_i'' - mu (1 - x_i^2) x_i' +
-// (K x)_i = 0, classic RK4 in stage form, s <= 1024 (register layouts)
+// (K x)_i = F_i cos(Omega t) (force optional), classic RK4 in stage form,
+// s <= 1024 (register layouts)
 // ---------------------------------------------------------------------------
 template <typename T>
 struct VdpLaunch {
@@ -434,6 +435,8 @@ struct VdpLaunch {
     ChainCoef<T> c;
     const double *m;           // [batch][s] masses
     double mu;
+    const double *f;           // [batch][s] F / m, or nullptr (no force)
+    const double *omega;       // [batch] force frequency
     const T *x0, *v0;
     T *state;                  // [4][batch][s] as for chains
     int64_t nsteps, n0, out_stride;

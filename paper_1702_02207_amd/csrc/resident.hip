@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kResidentThreads, (sizeof(T) == 8 && DPL == 16
         __hip_atomic_store(&r.ctl->exit_reason, reason, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-template <typename T, int DPL, int LPI>
+template <typename T, int DPL, int LPI, bool FORCED>
 __global__ void __launch_bounds__(kResidentThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 2)
     vdp_resident_kernel(VdpLaunch<T> a, ResidentRun<T> r) {
     __shared__ int go;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kResidentThreads, (sizeof(T) == 8 && DPL == 16
         t.store_mode = STORE_STATE | STORE_USER;
         t.xe = r.xf ? r.xf + (size_t)i * plane : r.xo;
         t.ve = r.vf ? r.vf + (size_t)i * plane : r.vo;
-        vdp_chain_run<T, DPL, LPI>(t, g);
+        vdp_chain_run<T, DPL, LPI, FORCED>(t, g);
         __threadfence_system();
         __syncthreads();
         if (threadIdx.x == 0)
@@ -220,7 +220,8 @@ osc_status launch_method(const ChainLaunch<T> &a, ChainConfig cfg, const Residen
 
 template <typename T, int DPL, int LPI>
 osc_status launch_vdp_layout(const VdpLaunch<T> &a, const ResidentRun<T> &r, hipStream_t st) {
-    void (*f)(VdpLaunch<T>, ResidentRun<T>) = &vdp_resident_kernel<T, DPL, LPI>;
+    void (*f)(VdpLaunch<T>, ResidentRun<T>) =
+        a.f ? &vdp_resident_kernel<T, DPL, LPI, true> : &vdp_resident_kernel<T, DPL, LPI, false>;
     const int64_t blocks = (a.batch * LPI + kResidentThreads - 1) / kResidentThreads;
     osc_status e = check_resident(reinterpret_cast<const void *>(f), blocks, kResidentThreads);
     if (e) return e;

@@ -1,11 +1,14 @@
 // Coupled Van der Pol chains: the chain of eq. (2) with a Van der Pol
-// element on every body,
-//     m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = 0,
+// element on every body, optionally driven by a harmonic force,
+//     m_i x_i'' - mu (1 - x_i^2) x_i' + (K x)_i = F_i cos(Omega t),
 // the nonlinear oscillators the paper's section 1 motivates the work with.
 //
 // Classic RK4 on the first-order system of section 3, in scaled time
-// (tau = t/h, w = h v, B = h^2 M^-1 K, g_i = h mu / m_i):
-//     x' = w,   w' = -B x + g (1 - x^2) w.
+// (tau = t/h, w = h v, B = h^2 M^-1 K, g_i = h mu / m_i, f = F / m):
+//     x' = w,   w' = -B x + g (1 - x^2) w + h^2 f cos(Omega h tau),
+// with the force's phase at the stage times t_n, t_n + h/2 (twice), t_n + h
+// taken from the FP64 rotation of the damped, driven kernel, re-anchored
+// exactly every 64 global steps, so that chunked runs give the same bits.
 // The linear Taylor form of the free chains does not apply (the right-hand
 // side is nonlinear), so the four stages are evaluated in turn.  With k_j
 // the stages' w-slopes, stage j's argument is (x + d_j, w + c_j) with
@@ -39,7 +42,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
-template <typename T, int DPL, int LPI>
+template <typename T, int DPL, int LPI, bool FORCED>
 __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64_t g) {
     constexpr bool COMP = std::is_same<T, float>::value;
     const int64_t b = g / LPI;
@@ -100,6 +103,17 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
         // zero beyond the chain (padding DOFs stay at rest)
 #pragma unroll
         for (int j = 0; j < DPL; ++j) gm[j] = md[j] > 0.0 ? (T)(h * a.mu / md[j]) : T(0);
+    }
+    T fh[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) fh[j] = T(0);
+    Phase ph{};
+    if constexpr (FORCED) {
+        double fd[DPL];
+        load(a.f, fd);
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) fh[j] = (T)(h * h * fd[j]);
+        if (active) ph.start(a.omega[b] * h, a.n0);
     }
     if (a.load_mode == LOAD_USER) {
         T v0[DPL];
@@ -186,12 +200,23 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
         }
     }
     while (n < nend) {
+        // the force's phase at the stage times (FP64), as scaled weights
+        T c0 = T(0), ch = T(0), c1 = T(0);
+        if constexpr (FORCED) {
+            if (n % kAnchor == 0) ph.set(n);
+            c0 = (T)ph.c;
+            ph.half();
+            ch = (T)ph.c;
+            ph.half();
+            c1 = (T)ph.c;
+        }
         T R[DPL], d[DPL], Bd[DPL], kc[DPL];
         bop(split, x, R);   // B x
         // stage 1 at (x, w)
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const T k = fma_t(gm[j] * fma_t(-x[j], x[j], T(1)), w[j], -R[j]);
+            T k = fma_t(gm[j] * fma_t(-x[j], x[j], T(1)), w[j], -R[j]);
+            if constexpr (FORCED) k = fma_t(fh[j], c0, k);
             kc[j] = k;
             xl[j] = fma_t(T(1.0 / 6.0), k, xl[j] + wl[j]);
             wl[j] = fma_t(T(1.0 / 6.0), k, wl[j]);
@@ -205,7 +230,8 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
             for (int j = 0; j < DPL; ++j) {
                 const T xt = x[j] + d[j];
                 const T wt = fma_t(T(0.5), kc[j], w[j]);
-                const T k = fma_t(gm[j] * fma_t(-xt, xt, T(1)), wt, -(R[j] + Bd[j]));
+                T k = fma_t(gm[j] * fma_t(-xt, xt, T(1)), wt, -(R[j] + Bd[j]));
+                if constexpr (FORCED) k = fma_t(fh[j], ch, k);
                 // d_3 = w/2 + k_1/4 = wt/2 (stage 2); d_4 = w + k_2/2 = wt (stage 3)
                 d[j] = st == 2 ? T(0.5) * wt : wt;
                 kc[j] = k;
@@ -219,7 +245,8 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
         for (int j = 0; j < DPL; ++j) {
             const T xt = x[j] + d[j];
             const T wt = w[j] + kc[j];
-            const T k = fma_t(gm[j] * fma_t(-xt, xt, T(1)), wt, -(R[j] + Bd[j]));
+            T k = fma_t(gm[j] * fma_t(-xt, xt, T(1)), wt, -(R[j] + Bd[j]));
+            if constexpr (FORCED) k = fma_t(fh[j], c1, k);
             wl[j] = fma_t(T(1.0 / 6.0), k, wl[j]);
             if constexpr (COMP) {
                 // x += w (its exact error kept) + the collected part; renormalise both pairs
@@ -269,16 +296,17 @@ __device__ __forceinline__ void vdp_chain_run(const VdpLaunch<T> &a, const int64
 
 // Two waves per SIMD; one for FP64 with 16 DOFs per lane (its stage values
 // do not fit half the registers).
-template <typename T, int DPL, int LPI>
+template <typename T, int DPL, int LPI, bool FORCED>
 __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 2) vdp_chain_kernel(VdpLaunch<T> a) {
-    vdp_chain_run<T, DPL, LPI>(a, (int64_t)blockIdx.x * kThreads + threadIdx.x);
+    vdp_chain_run<T, DPL, LPI, FORCED>(a, (int64_t)blockIdx.x * kThreads + threadIdx.x);
 }
 
 template <typename T, int DPL, int LPI>
 osc_status launch_layout(const VdpLaunch<T> &a, hipStream_t st) {
     const int64_t threads = a.batch * LPI;
     const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((vdp_chain_kernel<T, DPL, LPI>), dim3(blocks), dim3(kThreads), 0, st, a);
+    if (a.f) hipLaunchKernelGGL((vdp_chain_kernel<T, DPL, LPI, true>), dim3(blocks), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL((vdp_chain_kernel<T, DPL, LPI, false>), dim3(blocks), dim3(kThreads), 0, st, a);
     OSC_HIP(hipGetLastError());
     return OSC_OK;
 }

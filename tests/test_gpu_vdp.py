@@ -217,3 +217,71 @@ def test_vdp_degenerate_runs(prec, nsteps, stride):
         assert xf is None and vf is None
     scale = np.maximum(np.abs(rxe).max(axis=1), 1e-300)
     assert (np.abs(xe - rxe).max(axis=1) / scale).max() < TOL[prec]
+
+
+def _force(seed, m, k, batch, s):
+    """Forces of the order of the springs' (F ~ N(0, mean k)) at frequencies
+    near the chains' own (Omega ~ U[0.5, 2] x the median omega_max / 10)."""
+    rng = np.random.default_rng(seed)
+    F = rng.normal(0.0, 1.0, (batch, s)) * k.mean(axis=1, keepdims=True)
+    W = rng.uniform(0.5, 2.0, batch) * np.median(workloads.chain_omega_max(m, k)) / 10.0
+    return F, W
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("s,batch", [(2, 40), (8, 9), (64, 2), (300, 2), (1024, 2)])
+def test_forced_vdp_chains_match_oracle(s, batch, prec):
+    """The forced Van der Pol chain (a force set by osc_set_excitation on a
+    Van der Pol handle) against the oracle on every kind of layout; chunks of
+    333 steps (across the force phase's 64-step anchors) and the allocation-
+    free entry give the bits of one launch."""
+    nsteps, stride = 1500, 250
+    m, k, dt, mu, x0, v0 = _vdp(1100 + s, batch, s, nsteps, stride)
+    F, W = _force(1200 + s, m, k, batch, s)
+    sysm = osc.System("chain", "rk4", prec, m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(mu)
+        sysm.set_excitation(0.0, 0.0, F, W)
+        whole = _run(sysm, x0, v0, nsteps, stride, prec)
+        sysm.set_config(osc.CFG_STEPS_PER_LAUNCH, 333)
+        chunked = _run(sysm, x0, v0, nsteps, stride, prec)
+        static = _run(sysm, x0, v0, nsteps, stride, prec, static=True)
+    finally:
+        sysm.close()
+    for a, b, c in zip(whole, chunked, static):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, c)
+    x0r, v0r = _inputs(x0, v0, prec)
+    rx, rv, rxe, rve = oracle.chain_vdp(m, k, dt, mu, x0r, v0r, nsteps, stride, F=F, omega=W)
+    xf, vf, xe, ve = whole
+    ex, ev = oracle.rel_traj_err(xf, rx).max(), oracle.rel_traj_err(vf, rv).max()
+    print(f"forced vdp s={s} {prec}: x {ex:.2e} v {ev:.2e}")
+    assert max(ex, ev) < TOL[prec]
+    # the force matters in this run: the unforced Van der Pol chain ends elsewhere
+    ux, _, _, _ = oracle.chain_vdp(m, k, dt, mu, x0r, v0r, nsteps, stride)
+    assert oracle.rel_traj_err(ux, rx).max() > 100 * TOL[prec]
+
+
+def test_forced_vdp_resident_ticks_are_the_frames_of_one_integration():
+    """The forced Van der Pol pair stepped by the resident real-time kernel:
+    the states after the ticks equal the frames of one integration bit for
+    bit (the force's phase follows the global step)."""
+    import torch
+    m, k, dt, mu, x0, v0 = _vdp(1300, 2, 2, 400, 4)
+    F, W = _force(1301, m, k, 2, 2)
+    sysm = osc.System("chain", "rk4", "f64", m, k, dt).create()
+    try:
+        sysm.set_van_der_pol(mu)
+        sysm.set_excitation(0.0, 0.0, F, W)
+        X0, V0 = to_dev(x0, torch.float64), to_dev(v0, torch.float64)
+        xf, vf, _, _ = sysm.integrate(X0, V0, 400, 4)
+        sysm.sync()
+        ref_x, ref_v = xf[1:].cpu().numpy(), vf[1:].cpu().numpy()
+        with osc.Realtime(sysm, X0, V0, 4) as rt:
+            rx, rv, _, st = rt.run_resident(100e-6, 100)
+            rx, rv = rx.cpu().numpy(), rv.cpu().numpy()
+    finally:
+        sysm.close()
+    np.testing.assert_array_equal(rx, ref_x)
+    np.testing.assert_array_equal(rv, ref_v)
+    assert st["ticks"] == 100
