@@ -31,8 +31,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # register-pressure-first default schedule chains them one DOF at a time
 # (back-to-back dependent instructions), the ILP-first schedule interleaves
 # them.  The resident real-time kernels run the same per-lane integrator, and
-# the FP32 Van der Pol chains (vdp.hip; FP64 in vdp_f64.hip keeps the default:
-# with the ILP-first schedule its 16-DOF layout spills) have the same shape.
+# the free FP32 Van der Pol chains (vdp.hip) have the same shape.  The forced
+# FP32 (vdp_forced.hip) and FP64 (vdp_f64.hip) ones keep the default: with the
+# ILP-first schedule their 16-DOF layouts spill twice as much.
 PER_FILE = {name: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"] for name in ("chain.hip", "resident.hip", "vdp.hip")}
 
 

@@ -435,14 +435,14 @@ struct VdpLaunch {
     ChainCoef<T> c;
     const double *m;           // [batch][s] masses
     double mu;
-    const double *f;           // [batch][s] F / m, or nullptr (no force)
-    const double *omega;       // [batch] force frequency
     const T *x0, *v0;
     T *state;                  // [4][batch][s] as for chains
     int64_t nsteps, n0, out_stride;
     T *xf, *vf, *xe, *ve;
     int *nonfinite;
     int load_mode, store_mode;
+    const double *f;           // [batch][s] F / m, or nullptr (no force)
+    const double *omega;       // [batch] force frequency
 };
 template <typename T>
 osc_status vdp_launch(const VdpLaunch<T> &a, hipStream_t st);

@@ -26,9 +26,10 @@
 // Layouts: those of the damped, driven register kernel (one lane per chain
 // for s <= 8, one wave per chain beyond, DPP halos, no LDS), s <= 1024.
 //
-// This header holds the integrator; vdp.hip instantiates it for FP32 and
-// vdp_f64.hip for FP64, each built with the instruction scheduling that
-// suits its register pressure.
+// This header holds the integrator; vdp.hip instantiates the free FP32
+// kernels, vdp_forced.hip the forced FP32 ones and vdp_f64.hip both FP64
+// sets, each built with the instruction scheduling that suits its register
+// pressure.
 
 #pragma once
 
@@ -301,32 +302,39 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && DPL == 16) ? 1 : 
     vdp_chain_run<T, DPL, LPI, FORCED>(a, (int64_t)blockIdx.x * kThreads + threadIdx.x);
 }
 
-template <typename T, int DPL, int LPI>
+template <typename T, int DPL, int LPI, bool FORCED>
 osc_status launch_layout(const VdpLaunch<T> &a, hipStream_t st) {
     const int64_t threads = a.batch * LPI;
     const unsigned blocks = (unsigned)((threads + kThreads - 1) / kThreads);
-    if (a.f) hipLaunchKernelGGL((vdp_chain_kernel<T, DPL, LPI, true>), dim3(blocks), dim3(kThreads), 0, st, a);
-    else hipLaunchKernelGGL((vdp_chain_kernel<T, DPL, LPI, false>), dim3(blocks), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((vdp_chain_kernel<T, DPL, LPI, FORCED>), dim3(blocks), dim3(kThreads), 0, st, a);
     OSC_HIP(hipGetLastError());
     return OSC_OK;
 }
 
 }  // namespace
 
-template <typename T>
-osc_status vdp_launch(const VdpLaunch<T> &a, hipStream_t st) {
+// The kernels of one precision, with or without the force; each combination
+// is instantiated in a file of its own (the forced and free FP32 kernels
+// take different instruction schedules).
+template <typename T, bool FORCED>
+osc_status vdp_launch_as(const VdpLaunch<T> &a, hipStream_t st) {
     if (a.batch == 0) return OSC_OK;
     const int s = a.s;
-    if (s <= 1) return launch_layout<T, 1, 1>(a, st);
-    if (s <= 2) return launch_layout<T, 2, 1>(a, st);
-    if (s <= 4) return launch_layout<T, 4, 1>(a, st);
-    if (s <= 8) return launch_layout<T, 8, 1>(a, st);
-    if (s <= 64) return launch_layout<T, 1, 64>(a, st);
-    if (s <= 128) return launch_layout<T, 2, 64>(a, st);
-    if (s <= 256) return launch_layout<T, 4, 64>(a, st);
-    if (s <= 512) return launch_layout<T, 8, 64>(a, st);
-    if (s <= 1024) return launch_layout<T, 16, 64>(a, st);
+    if (s <= 1) return launch_layout<T, 1, 1, FORCED>(a, st);
+    if (s <= 2) return launch_layout<T, 2, 1, FORCED>(a, st);
+    if (s <= 4) return launch_layout<T, 4, 1, FORCED>(a, st);
+    if (s <= 8) return launch_layout<T, 8, 1, FORCED>(a, st);
+    if (s <= 64) return launch_layout<T, 1, 64, FORCED>(a, st);
+    if (s <= 128) return launch_layout<T, 2, 64, FORCED>(a, st);
+    if (s <= 256) return launch_layout<T, 4, 64, FORCED>(a, st);
+    if (s <= 512) return launch_layout<T, 8, 64, FORCED>(a, st);
+    if (s <= 1024) return launch_layout<T, 16, 64, FORCED>(a, st);
     return fail(OSC_ENOTSUP, "Van der Pol chains take s <= 1024");
+}
+
+template <typename T>
+osc_status vdp_launch(const VdpLaunch<T> &a, hipStream_t st) {
+    return a.f ? vdp_launch_as<T, true>(a, st) : vdp_launch_as<T, false>(a, st);
 }
 
 }  // namespace osc
